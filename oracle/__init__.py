@@ -1,0 +1,283 @@
+"""GPZ CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes wrapper around ``gpz_oracle.c``: a plain, slow, obviously-correct
+CPU implementation of the GPZ compressor (arXiv 2508.10305, Sec. 4.1-4.4 and
+Sec. 3.2).  It exists to check the HIP implementation; only the tests, the
+smoke check and the benchmark's CPU-baseline leg may import it.  It shares no
+code with the HIP path and never calls into it.
+
+Build with ``oracle.build_oracle()`` (gcc, ``-ffp-contract=off``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gpz_oracle.c")
+LIB = os.path.join(HERE, "_build", "liboracle.so")
+
+OK, EINVAL, ENOSPC, ECORRUPT = 0, -1, -2, -3
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def build_oracle() -> str:
+    """Compile the oracle shared library (always recompiles)."""
+    os.makedirs(os.path.dirname(LIB), exist_ok=True)
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build_oracle()
+        L = ctypes.CDLL(LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        f32p = ctypes.POINTER(ctypes.c_float)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        fpp = ctypes.POINTER(f32p)
+        L.oracle_block_min.restype = ctypes.c_float
+        L.oracle_block_min.argtypes = [f32p, ctypes.c_uint32]
+        L.oracle_quantize.restype = ctypes.c_uint32
+        L.oracle_quantize.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.POINTER(ctypes.c_int)]
+        L.oracle_sort_rle.restype = ctypes.c_uint32
+        L.oracle_sort_rle.argtypes = [u32p, ctypes.c_uint32, u32p, u32p, u32p, u32p]
+        L.oracle_max_bytes.restype = ctypes.c_uint64
+        L.oracle_max_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.oracle_compress.restype = ctypes.c_int
+        L.oracle_compress.argtypes = [fpp, ctypes.c_uint64, ctypes.c_uint32, f32p, ctypes.c_uint32,
+                                      ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.c_uint64, u64p,
+                                      u32p]
+        L.oracle_encode_block.restype = ctypes.c_int
+        L.oracle_encode_block.argtypes = [fpp, ctypes.c_uint32, ctypes.c_uint32, f32p,
+                                          ctypes.c_uint32, ctypes.c_uint32, u32p, ctypes.c_uint32,
+                                          u32p, u32p]
+        L.oracle_block_trace.restype = ctypes.c_int
+        L.oracle_block_trace.argtypes = [fpp, ctypes.c_uint32, ctypes.c_uint32, f32p,
+                                         ctypes.c_uint32, ctypes.c_uint32, f32p, u32p, u32p, u8p,
+                                         u32p, u32p, u32p, u32p, u32p, u32p, u32p]
+        L.oracle_inspect.restype = ctypes.c_int
+        L.oracle_inspect.argtypes = [u8p, ctypes.c_uint64, u64p]
+        L.oracle_decompress.restype = ctypes.c_int
+        L.oracle_decompress.argtypes = [u8p, ctypes.c_uint64, fpp, ctypes.c_uint64, ctypes.c_uint32]
+        L.oracle_bound_check.restype = ctypes.c_int
+        L.oracle_bound_check.argtypes = [fpp, fpp, u32p, ctypes.c_uint64, ctypes.c_uint32, f32p,
+                                         u64p, f64p]
+        L.oracle_field_range.restype = ctypes.c_int
+        L.oracle_field_range.argtypes = [fpp, ctypes.c_uint64, ctypes.c_uint32, f32p]
+        L.oracle_rel_to_abs.restype = ctypes.c_float
+        L.oracle_rel_to_abs.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        _lib = L
+    return _lib
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _field_ptrs(fields: Sequence[np.ndarray]):
+    arr = (ctypes.POINTER(ctypes.c_float) * max(1, len(fields)))()
+    for i, f in enumerate(fields):
+        arr[i] = _ptr(f, ctypes.c_float)
+    return arr
+
+
+def _ebs(eb, F: int) -> np.ndarray:
+    e = np.asarray(eb, dtype=np.float32)
+    if e.ndim == 0:
+        e = np.full(F, e, dtype=np.float32)
+    if e.shape != (F,):
+        raise ValueError("eb must be a scalar or one value per field")
+    return np.ascontiguousarray(e)
+
+
+# ---------------------------------------------------------------- steps
+
+def block_min(x) -> float:
+    x = _f32(x)
+    return float(np.float32(lib().oracle_block_min(_ptr(x, ctypes.c_float), x.size)))
+
+
+def quantize(x: float, lo: float, eb: float):
+    """Grid index and outlier flag of one value (Sec. 4.1 equation)."""
+    o = ctypes.c_int(0)
+    q = lib().oracle_quantize(ctypes.c_float(x), ctypes.c_float(lo), ctypes.c_float(eb),
+                              ctypes.byref(o))
+    return int(q), bool(o.value)
+
+
+def sort_rle(keys: Sequence[int]):
+    """Stable sort + run-length + delta coding of a key list (Sec. 4.2-4.3).
+    Returns (perm, uniques, counts, deltas)."""
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    n = k.size
+    perm = np.zeros(max(1, n), np.uint32)
+    uniq = np.zeros(max(1, n), np.uint32)
+    cnt = np.zeros(max(1, n), np.uint32)
+    dl = np.zeros(max(1, n), np.uint32)
+    U = lib().oracle_sort_rle(_ptr(k, ctypes.c_uint32), n, _ptr(perm, ctypes.c_uint32),
+                              _ptr(uniq, ctypes.c_uint32), _ptr(cnt, ctypes.c_uint32),
+                              _ptr(dl, ctypes.c_uint32))
+    return perm[:n], uniq[:U], cnt[:U], dl[:U]
+
+
+def max_bytes(n: int, F: int, B: int = 1024) -> int:
+    return int(lib().oracle_max_bytes(n, F, B))
+
+
+# ---------------------------------------------------------------- whole pipeline
+
+def compress(fields: Sequence[np.ndarray], eb, B: int = 1024, K: int = 3,
+             KF: Optional[int] = None, want_perm: bool = False):
+    """Compress SoA float32 fields; returns (stream bytes as np.uint8, perm or None)."""
+    fields = [_f32(f) for f in fields]
+    F = len(fields)
+    n = fields[0].size if F else 0
+    if KF is None:
+        KF = min(F, 3)
+    e = _ebs(eb, F)
+    cap = max_bytes(n, F, B) if F else 64
+    out = np.zeros(max(cap, 4), np.uint8)
+    nbytes = ctypes.c_uint64(0)
+    perm = np.zeros(max(1, n), np.uint32) if want_perm else None
+    rc = lib().oracle_compress(_field_ptrs(fields), n, F, _ptr(e, ctypes.c_float), B, K, KF,
+                               _ptr(out, ctypes.c_uint8), out.size, ctypes.byref(nbytes),
+                               _ptr(perm, ctypes.c_uint32) if want_perm else None)
+    if rc != OK:
+        raise OracleError(rc, "compress")
+    return out[: nbytes.value].copy(), (perm[:n] if want_perm else None)
+
+
+def encode_block(fields: Sequence[np.ndarray], eb, K: int = 3, KF: Optional[int] = None):
+    """Record words of one block (all of ``fields``), and its permutation."""
+    fields = [_f32(f) for f in fields]
+    F = len(fields)
+    n = fields[0].size
+    if KF is None:
+        KF = min(F, 3)
+    e = _ebs(eb, F)
+    cap = 1 + F * n
+    rec = np.zeros(cap, np.uint32)
+    rw = ctypes.c_uint32(0)
+    perm = np.zeros(n, np.uint32)
+    rc = lib().oracle_encode_block(_field_ptrs(fields), n, F, _ptr(e, ctypes.c_float), K, KF,
+                                   _ptr(rec, ctypes.c_uint32), cap, ctypes.byref(rw),
+                                   _ptr(perm, ctypes.c_uint32))
+    if rc != OK:
+        raise OracleError(rc, "encode_block")
+    return rec[: rw.value].copy(), perm
+
+
+def block_trace(fields: Sequence[np.ndarray], eb, K: int = 3, KF: Optional[int] = None) -> dict:
+    """Intermediate results of stages 1-3 for one block."""
+    fields = [_f32(f) for f in fields]
+    F = len(fields)
+    n = fields[0].size
+    if KF is None:
+        KF = min(F, 3)
+    e = _ebs(eb, F)
+    lo = np.zeros(F, np.float32)
+    s = np.zeros(3, np.uint32)
+    q = np.zeros(F * n, np.uint32)
+    outl = np.zeros(F * n, np.uint8)
+    key = np.zeros(n, np.uint32)
+    perm = np.zeros(n, np.uint32)
+    uniq = np.zeros(n, np.uint32)
+    cnt = np.zeros(n, np.uint32)
+    widths = np.zeros(2 + F, np.uint32)
+    U = ctypes.c_uint32(0)
+    cw = ctypes.c_uint32(0)
+    P = lambda a, t=ctypes.c_uint32: _ptr(a, t)
+    rc = lib().oracle_block_trace(_field_ptrs(fields), n, F, _ptr(e, ctypes.c_float), K, KF,
+                                  P(lo, ctypes.c_float), P(s), P(q), P(outl, ctypes.c_uint8),
+                                  P(key), P(perm), P(uniq), P(cnt), P(widths), ctypes.byref(U),
+                                  ctypes.byref(cw))
+    if rc != OK:
+        raise OracleError(rc, "block_trace")
+    u = U.value
+    return dict(lo=lo, s=s[:KF], q=q.reshape(F, n), outlier=outl.reshape(F, n).astype(bool),
+                key=key, perm=perm, uniq=uniq[:u], count=cnt[:u], w_gap=int(widths[0]),
+                w_cnt=int(widths[1]), w=widths[2:].copy(), U=u, coded_words=cw.value)
+
+
+def inspect(stream: np.ndarray) -> dict:
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    info = np.zeros(7, np.uint64)
+    rc = lib().oracle_inspect(_ptr(s, ctypes.c_uint8), s.size, _ptr(info, ctypes.c_uint64))
+    if rc != OK:
+        raise OracleError(rc, "inspect")
+    keys = ("n", "F", "B", "K", "KF", "nblocks", "bytes")
+    return {k: int(v) for k, v in zip(keys, info)}
+
+
+def decompress(stream: np.ndarray, n: int, F: int) -> List[np.ndarray]:
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    outs = [np.zeros(max(1, n), np.float32) for _ in range(F)]
+    rc = lib().oracle_decompress(_ptr(s, ctypes.c_uint8), s.size, _field_ptrs(outs), n, F)
+    if rc != OK:
+        raise OracleError(rc, "decompress")
+    return [o[:n] for o in outs]
+
+
+def decompress_status(stream: np.ndarray, n: int, F: int) -> int:
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    outs = [np.zeros(max(1, n), np.float32) for _ in range(F)]
+    return int(lib().oracle_decompress(_ptr(s, ctypes.c_uint8), s.size, _field_ptrs(outs), n, F))
+
+
+def bound_check(orig: Sequence[np.ndarray], recon: Sequence[np.ndarray], eb, perm=None):
+    orig = [_f32(f) for f in orig]
+    recon = [_f32(f) for f in recon]
+    F = len(orig)
+    n = orig[0].size
+    e = _ebs(eb, F)
+    viol = np.zeros(F, np.uint64)
+    mx = np.zeros(F, np.float64)
+    p = None if perm is None else np.ascontiguousarray(perm, dtype=np.uint32)
+    lib().oracle_bound_check(_field_ptrs(orig), _field_ptrs(recon),
+                             None if p is None else _ptr(p, ctypes.c_uint32), n, F,
+                             _ptr(e, ctypes.c_float), _ptr(viol, ctypes.c_uint64),
+                             _ptr(mx, ctypes.c_double))
+    return viol, mx
+
+
+def field_range(fields: Sequence[np.ndarray]) -> np.ndarray:
+    fields = [_f32(f) for f in fields]
+    F = len(fields)
+    mm = np.zeros(2 * F, np.float32)
+    lib().oracle_field_range(_field_ptrs(fields), fields[0].size, F, _ptr(mm, ctypes.c_float))
+    return mm.reshape(F, 2)
+
+
+def rel_to_abs(rel: float, lo: float, hi: float) -> float:
+    return float(np.float32(lib().oracle_rel_to_abs(rel, lo, hi)))
+
+
+def rel_ebs(fields: Sequence[np.ndarray], rel: float) -> np.ndarray:
+    mm = field_range(fields)
+    return np.array([rel_to_abs(rel, float(a), float(b)) for a, b in mm], np.float32)

@@ -1,0 +1,746 @@
+/*
+ * GPZ CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct C implementation of the GPZ
+ * error-bounded particle compressor (arXiv 2508.10305): spatial
+ * quantization (Sec. 4.1), in-block sorting by segment ID (Sec. 4.2),
+ * run-length + delta + fixed-length encoding (Sec. 4.3) and compaction by
+ * a prefix sum of block sizes (Sec. 4.4), plus the reverse (Sec. 3.2:
+ * decompression reverses the steps, without un-sorting).
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this code.  It shares nothing with the HIP implementation: no
+ * headers, no tables, no helpers.  The byte format it writes is the one
+ * frozen in the design notes ("stream format v1"); every rule the paper
+ * leaves open is fixed there and restated next to the code that applies it.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fPIC -shared
+ * (no contraction, IEEE single/double arithmetic, round-to-nearest-even).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOSPC (-2)
+#define OR_ECORRUPT (-3)
+
+#define OR_MAGIC 0x315A5047u /* "GPZ1" little-endian */
+#define OR_VERSION 1u
+#define OR_HEADER_WORDS 8u
+#define OR_SUPER 64u /* blocks per superblock offset entry */
+#define OR_QMAX 16777215.0f /* largest grid index: 2^24 - 1 */
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                        */
+/* ------------------------------------------------------------------ */
+
+/* Number of significant bits of v (0 for v == 0): the "bit-width" that
+ * fixed-length coding uses to drop leading zeros (Sec. 4.3). */
+static uint32_t bit_width(uint32_t v) {
+    uint32_t w = 0;
+    while (v) {
+        w++;
+        v >>= 1;
+    }
+    return w;
+}
+
+static uint32_t f2u(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+static float u2f(uint32_t u) {
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+static int eb_valid(float eb) {
+    /* 2^-120 <= eb <= 2^120 keeps 2*eb and 1/(2*eb) finite and normal. */
+    return isfinite(eb) && eb >= 0x1p-120f && eb <= 0x1p120f;
+}
+
+static int block_size_valid(uint32_t B) {
+    return B >= 64 && B <= 4096 && (B & (B - 1)) == 0;
+}
+
+/* Bit writer for fixed-length coding: value i of an array occupies bits
+ * [i*w, i*w + w) of an LSB-first little-endian word stream (Sec. 4.3:
+ * every value of an array is written with one uniform bit-width).  Written
+ * one bit at a time on purpose. */
+static void put_bits(uint32_t *words, uint64_t bitpos, uint32_t value, uint32_t w) {
+    for (uint32_t b = 0; b < w; b++) {
+        if ((value >> b) & 1u) {
+            uint64_t p = bitpos + b;
+            words[p / 32] |= 1u << (p % 32);
+        }
+    }
+}
+
+static uint32_t get_bits(const uint32_t *words, uint64_t bitpos, uint32_t w) {
+    uint32_t v = 0;
+    for (uint32_t b = 0; b < w; b++) {
+        uint64_t p = bitpos + b;
+        if ((words[p / 32] >> (p % 32)) & 1u) v |= 1u << b;
+    }
+    return v;
+}
+
+static uint32_t words_for(uint64_t count, uint32_t w) {
+    return (uint32_t)((count * (uint64_t)w + 31) / 32);
+}
+
+/* ------------------------------------------------------------------ */
+/* Stage 1: spatial quantization (Sec. 4.1)                             */
+/* ------------------------------------------------------------------ */
+
+/* Block boundary minimum (Sec. 4.1: per-axis extrema of the block).  Only
+ * finite values take part; a block with no finite value uses 0; a minimum
+ * equal to zero is stored as +0.0 so that its bits do not depend on the
+ * order in which -0.0 and +0.0 were met. */
+float oracle_block_min(const float *x, uint32_t n) {
+    int found = 0;
+    float lo = 0.0f;
+    for (uint32_t i = 0; i < n; i++) {
+        if (!isfinite(x[i])) continue;
+        if (!found || x[i] < lo) lo = x[i];
+        found = 1;
+    }
+    if (!found || lo == 0.0f) lo = 0.0f;
+    return lo;
+}
+
+/* Grid index of one value (Sec. 4.1 equation: m*segId + segOffset =
+ * (p - min)/(2 eb)).  The division is a multiplication by the reciprocal
+ * 1/(2 eb) rounded once to float (Sec. 5.1, division elimination); the
+ * result is rounded to the nearest integer, ties to even.  The value is an
+ * outlier, to be stored verbatim, when the index falls outside [0, 2^24-1]
+ * (32-bit intermediates, Sec. 5.3) or when the float32 reconstruction
+ * fma(q, 2 eb, min) (Sec. 5.1, explicit FMA) misses the bound; the bound
+ * test is |xr - x| <= eb in IEEE double. */
+uint32_t oracle_quantize(float x, float lo, float eb, int *outlier) {
+    float twoeb = 2.0f * eb;
+    float inv = 1.0f / twoeb;
+    float diff = x - lo;
+    float t = diff * inv;
+    int in_range = (t >= 0.0f) && (t <= OR_QMAX);
+    uint32_t q = 0;
+    if (in_range) q = (uint32_t)rintf(t);
+    float xr = fmaf((float)q, twoeb, lo);
+    int ok = in_range && (fabs((double)xr - (double)x) <= (double)eb);
+    *outlier = !ok;
+    return q;
+}
+
+/* Value reconstruction used by decompression (Sec. 5.1, FMA). */
+static float reconstruct(uint32_t q, float twoeb, float lo) {
+    return fmaf((float)q, twoeb, lo);
+}
+
+/* Segment split of one key axis.  The segment size m is the power of two
+ * 2^s with s = max(0, W - K), W the bit-width of the largest grid index of
+ * the axis in the block: the occupied range is cut into 2^K segments, a
+ * size proportional to max - min (Sec. 4.1), and the power-of-two modulus
+ * becomes a bit mask (Sec. 5.1, modulo elimination). */
+static uint32_t seg_shift(uint32_t qmax, uint32_t K) {
+    uint32_t W = bit_width(qmax);
+    return W > K ? W - K : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Stage 2: in-block sort by segment ID (Sec. 4.2)                      */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t key;
+    uint32_t idx;
+} key_idx;
+
+static int cmp_key_idx(const void *a, const void *b) {
+    const key_idx *x = (const key_idx *)a, *y = (const key_idx *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;
+    return 0;
+}
+
+/* Stable sort of a block by segment ID: ascending ID, equal IDs keep input
+ * order (the radix sort of Sec. 4.2 is stable). perm[p] = input index of
+ * the particle placed at position p. */
+static void sort_by_segment(const uint32_t *segId, uint32_t n, uint32_t *perm) {
+    key_idx *t = (key_idx *)malloc(sizeof(key_idx) * (n ? n : 1));
+    for (uint32_t i = 0; i < n; i++) {
+        t[i].key = segId[i];
+        t[i].idx = i;
+    }
+    qsort(t, n, sizeof(key_idx), cmp_key_idx);
+    for (uint32_t i = 0; i < n; i++) perm[i] = t[i].idx;
+    free(t);
+}
+
+/* ------------------------------------------------------------------ */
+/* Stage 3: run-length + delta encoding (Sec. 4.3)                      */
+/* ------------------------------------------------------------------ */
+
+/* Run-length coding of sorted IDs: the distinct IDs in ascending order and
+ * how many particles carry each.  Returns the number of runs U. */
+static uint32_t run_length(const uint32_t *sorted, uint32_t n, uint32_t *uniq, uint32_t *count) {
+    uint32_t U = 0;
+    for (uint32_t p = 0; p < n; p++) {
+        if (p == 0 || sorted[p] != sorted[p - 1]) {
+            uniq[U] = sorted[p];
+            count[U] = 0;
+            U++;
+        }
+        count[U - 1]++;
+    }
+    return U;
+}
+
+/* Exposed step (for the worked example of Sec. 4.2): stable sort of n keys
+ * followed by run-length and delta coding.  delta[j] = uniq[j] - uniq[j-1]
+ * with uniq[-1] taken as 0. */
+uint32_t oracle_sort_rle(const uint32_t *keys, uint32_t n, uint32_t *perm, uint32_t *uniq,
+                         uint32_t *count, uint32_t *delta) {
+    uint32_t *sorted = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    sort_by_segment(keys, n, perm);
+    for (uint32_t p = 0; p < n; p++) sorted[p] = keys[perm[p]];
+    uint32_t U = run_length(sorted, n, uniq, count);
+    for (uint32_t j = 0; j < U; j++) delta[j] = uniq[j] - (j ? uniq[j - 1] : 0);
+    free(sorted);
+    return U;
+}
+
+/* ------------------------------------------------------------------ */
+/* One block: stages 1-3 and the record layout                          */
+/* ------------------------------------------------------------------ */
+
+/* Everything the encoder derives for one block, kept for inspection. */
+typedef struct {
+    uint32_t n, F, K, KF, U;
+    float lo[64];
+    uint32_t s[3];
+    uint32_t w_gap, w_cnt, w[64], nout[64];
+    uint32_t *q;       /* F*n grid indices, input order, field-major */
+    uint8_t *outlier;  /* F*n flags, input order */
+    uint32_t *key;     /* n linearised segment IDs, input order */
+    uint32_t *perm;    /* n: position -> input index */
+    uint32_t *uniq;    /* U */
+    uint32_t *count;   /* U */
+    uint32_t coded_words;
+} block_state;
+
+static void block_free(block_state *st) {
+    free(st->q);
+    free(st->outlier);
+    free(st->key);
+    free(st->perm);
+    free(st->uniq);
+    free(st->count);
+}
+
+/* Stages 1-3 for one block of n particles: x[f] points at the block's
+ * values of field f. */
+static void analyse_block(const float *const *x, uint32_t n, uint32_t F, const float *eb,
+                          uint32_t K, uint32_t KF, block_state *st) {
+    memset(st, 0, sizeof(*st));
+    st->n = n;
+    st->F = F;
+    st->K = K;
+    st->KF = KF;
+    st->q = (uint32_t *)calloc((size_t)F * n + 1, sizeof(uint32_t));
+    st->outlier = (uint8_t *)calloc((size_t)F * n + 1, 1);
+    st->key = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
+    st->perm = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
+    st->uniq = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
+    st->count = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
+
+    /* Stage 1: block minimum and grid index of every value of every field. */
+    for (uint32_t f = 0; f < F; f++) {
+        st->lo[f] = oracle_block_min(x[f], n);
+        for (uint32_t i = 0; i < n; i++) {
+            int o;
+            st->q[(size_t)f * n + i] = oracle_quantize(x[f][i], st->lo[f], eb[f], &o);
+            st->outlier[(size_t)f * n + i] = (uint8_t)o;
+        }
+    }
+
+    /* Stage 1 (cont.): segment ID and offset per key axis; the per-axis
+     * segment IDs are linearised into one ID, axis 0 most significant. */
+    for (uint32_t a = 0; a < KF; a++) {
+        uint32_t qmax = 0;
+        for (uint32_t i = 0; i < n; i++)
+            if (st->q[(size_t)a * n + i] > qmax) qmax = st->q[(size_t)a * n + i];
+        st->s[a] = seg_shift(qmax, K);
+    }
+    for (uint32_t i = 0; i < n; i++) {
+        uint32_t segId = 0;
+        for (uint32_t a = 0; a < KF; a++) {
+            uint32_t q = st->q[(size_t)a * n + i];
+            uint32_t m = 1u << st->s[a];
+            uint32_t segId_a = q / m; /* same as q >> s (power-of-two m) */
+            segId = segId * (1u << K) + segId_a;
+        }
+        st->key[i] = segId;
+    }
+
+    /* Stage 2: stable in-block sort by segment ID. */
+    sort_by_segment(st->key, n, st->perm);
+
+    /* Stage 3: run-length coding of the sorted IDs, then delta coding of the
+     * distinct IDs.  Consecutive distinct IDs differ by at least one and
+     * every run has at least one particle, so "delta - 1" (first ID taken
+     * relative to -1) and "count - 1" are stored. */
+    uint32_t *sorted = (uint32_t *)calloc(n + 1, sizeof(uint32_t));
+    for (uint32_t p = 0; p < n; p++) sorted[p] = st->key[st->perm[p]];
+    st->U = run_length(sorted, n, st->uniq, st->count);
+    free(sorted);
+    uint32_t gmax = 0, cmax = 0;
+    for (uint32_t j = 0; j < st->U; j++) {
+        uint32_t gap = j == 0 ? st->uniq[0] : st->uniq[j] - st->uniq[j - 1] - 1;
+        if (gap > gmax) gmax = gap;
+        if (st->count[j] - 1 > cmax) cmax = st->count[j] - 1;
+    }
+    st->w_gap = bit_width(gmax);
+    st->w_cnt = bit_width(cmax);
+
+    /* Fixed-length widths of the per-particle arrays: segment offsets for
+     * key axes, whole grid indices for the other fields. */
+    uint32_t words = 2 + words_for(st->U, st->w_gap) + words_for(st->U, st->w_cnt);
+    for (uint32_t f = 0; f < F; f++) {
+        uint32_t vmax = 0, nout = 0;
+        for (uint32_t i = 0; i < n; i++) {
+            uint32_t q = st->q[(size_t)f * n + i];
+            uint32_t v = f < KF ? (q & ((1u << st->s[f]) - 1u)) /* q mod m */ : q;
+            if (v > vmax) vmax = v;
+            nout += st->outlier[(size_t)f * n + i];
+        }
+        st->w[f] = bit_width(vmax);
+        st->nout[f] = nout;
+        words += 2 + words_for(n, st->w[f]) + 2 * nout;
+    }
+    st->coded_words = words;
+}
+
+/* Record of one block (words).  Coded layout:
+ *   h0 = mode 0 | U << 2
+ *   h1 = w_gap | w_cnt << 5 | s0 << 10 | s1 << 15 | s2 << 20
+ *   gaps   : U values of w_gap bits   (uniq[j] - uniq[j-1] - 1, uniq[-1] = -1)
+ *   counts : U values of w_cnt bits   (count - 1)
+ *   per field f:
+ *     lo_f bits ; w_f | nout_f << 5 ; n values of w_f bits in sorted order ;
+ *     nout_f pairs (position, raw float bits), ascending position
+ * Raw layout (when the coded record would not be smaller):
+ *   h0 = 1 ; then the F x n input floats, field-major, input order. */
+static uint32_t raw_words(uint32_t n, uint32_t F) { return 1 + F * n; }
+
+static uint32_t write_block(const float *const *x, const block_state *st, uint32_t *rec) {
+    uint32_t n = st->n, F = st->F, KF = st->KF;
+    uint32_t raw = raw_words(n, F);
+    if (st->coded_words >= raw) {
+        rec[0] = 1;
+        for (uint32_t f = 0; f < F; f++)
+            for (uint32_t i = 0; i < n; i++) rec[1 + f * n + i] = f2u(x[f][i]);
+        return raw;
+    }
+    memset(rec, 0, sizeof(uint32_t) * st->coded_words);
+    uint32_t pos = 0;
+    rec[pos++] = 0u | (st->U << 2);
+    rec[pos++] = st->w_gap | (st->w_cnt << 5) | (st->s[0] << 10) | (st->s[1] << 15) | (st->s[2] << 20);
+    for (uint32_t j = 0; j < st->U; j++) {
+        uint32_t gap = j == 0 ? st->uniq[0] : st->uniq[j] - st->uniq[j - 1] - 1;
+        put_bits(rec + pos, (uint64_t)j * st->w_gap, gap, st->w_gap);
+    }
+    pos += words_for(st->U, st->w_gap);
+    for (uint32_t j = 0; j < st->U; j++)
+        put_bits(rec + pos, (uint64_t)j * st->w_cnt, st->count[j] - 1, st->w_cnt);
+    pos += words_for(st->U, st->w_cnt);
+    for (uint32_t f = 0; f < F; f++) {
+        rec[pos++] = f2u(st->lo[f]);
+        rec[pos++] = st->w[f] | (st->nout[f] << 5);
+        for (uint32_t p = 0; p < n; p++) {
+            uint32_t q = st->q[(size_t)f * n + st->perm[p]];
+            uint32_t v = f < KF ? (q & ((1u << st->s[f]) - 1u)) : q;
+            put_bits(rec + pos, (uint64_t)p * st->w[f], v, st->w[f]);
+        }
+        pos += words_for(n, st->w[f]);
+        for (uint32_t p = 0; p < n; p++) {
+            uint32_t i = st->perm[p];
+            if (st->outlier[(size_t)f * n + i]) {
+                rec[pos++] = p;
+                rec[pos++] = f2u(x[f][i]);
+            }
+        }
+    }
+    return pos;
+}
+
+/* ------------------------------------------------------------------ */
+/* Parameter checks and sizes                                           */
+/* ------------------------------------------------------------------ */
+
+static int params_valid(uint32_t F, uint32_t B, uint32_t K, uint32_t KF) {
+    if (F < 1 || F > 64) return 0;
+    if (!block_size_valid(B)) return 0;
+    if (KF < 1 || KF > 3 || KF > F) return 0;
+    if (K > 5) return 0;
+    return 1;
+}
+
+static uint64_t nblocks_of(uint64_t n, uint32_t B) { return (n + B - 1) / B; }
+static uint64_t nsuper_of(uint64_t nb) { return (nb + OR_SUPER - 1) / OR_SUPER; }
+
+static uint64_t prefix_words(uint64_t n, uint32_t F, uint32_t B) {
+    uint64_t nb = nblocks_of(n, B);
+    return OR_HEADER_WORDS + 2 * nsuper_of(nb) + F + nb;
+}
+
+/* Largest stream: every block stored raw. */
+uint64_t oracle_max_bytes(uint64_t n, uint32_t F, uint32_t B) {
+    if (F < 1 || F > 64 || !block_size_valid(B)) return 0;
+    return 4 * (prefix_words(n, F, B) + nblocks_of(n, B) + (uint64_t)F * n);
+}
+
+/* ------------------------------------------------------------------ */
+/* Stage 4: compaction (Sec. 4.4) -- full compress                       */
+/* ------------------------------------------------------------------ */
+
+/* Stream layout (words, little-endian):
+ *   0: magic "GPZ1"   1: version   2-3: N (u64)   4: F   5: B
+ *   6: K | KF << 8    7: number of blocks
+ *   superblock table: one u64 per 64 blocks = word offset of the
+ *                     superblock's first record inside the record area
+ *   eb table: F float bits
+ *   length table: record length in words, one per block
+ *   records, in block order.
+ * The record offsets are the exclusive prefix sum of the record lengths
+ * (Sec. 4.4). */
+int oracle_compress(const float *const *fields, uint64_t n, uint32_t F, const float *eb, uint32_t B,
+                    uint32_t K, uint32_t KF, uint8_t *out, uint64_t cap, uint64_t *out_bytes,
+                    uint32_t *perm_out) {
+    if (!params_valid(F, B, K, KF)) return OR_EINVAL;
+    for (uint32_t f = 0; f < F; f++)
+        if (!eb_valid(eb[f])) return OR_EINVAL;
+    if (n > 0 && (fields == NULL || out == NULL)) return OR_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < F; f++)
+        if (fields[f] == NULL) return OR_EINVAL;
+
+    uint64_t nb = nblocks_of(n, B), ns = nsuper_of(nb);
+    uint64_t pre = prefix_words(n, F, B);
+    uint32_t *lens = (uint32_t *)calloc(nb + 1, sizeof(uint32_t));
+    uint32_t **recs = (uint32_t **)calloc(nb + 1, sizeof(uint32_t *));
+    uint64_t total = pre;
+    for (uint64_t b = 0; b < nb; b++) {
+        uint32_t nn = (uint32_t)((b + 1) * B <= n ? B : n - b * B);
+        const float *x[64];
+        for (uint32_t f = 0; f < F; f++) x[f] = fields[f] + b * B;
+        block_state st;
+        analyse_block(x, nn, F, eb, K, KF, &st);
+        uint32_t cap_words = st.coded_words > raw_words(nn, F) ? st.coded_words : raw_words(nn, F);
+        recs[b] = (uint32_t *)calloc(cap_words, sizeof(uint32_t));
+        lens[b] = write_block(x, &st, recs[b]);
+        if (perm_out) {
+            int raw = recs[b][0] == 1u;
+            for (uint32_t p = 0; p < nn; p++) perm_out[b * B + p] = (uint32_t)(b * B + (raw ? p : st.perm[p]));
+        }
+        block_free(&st);
+        total += lens[b];
+    }
+    *out_bytes = 4 * total;
+    int rc = OR_OK;
+    if (4 * total > cap || (total > 0 && out == NULL)) {
+        rc = OR_ENOSPC;
+    } else {
+        uint32_t *w = (uint32_t *)malloc(4 * total);
+        w[0] = OR_MAGIC;
+        w[1] = OR_VERSION;
+        w[2] = (uint32_t)(n & 0xFFFFFFFFu);
+        w[3] = (uint32_t)(n >> 32);
+        w[4] = F;
+        w[5] = B;
+        w[6] = K | (KF << 8);
+        w[7] = (uint32_t)nb;
+        uint32_t *sup = w + OR_HEADER_WORDS;
+        uint32_t *ebt = sup + 2 * ns;
+        uint32_t *lt = ebt + F;
+        uint32_t *rec = lt + nb;
+        for (uint32_t f = 0; f < F; f++) ebt[f] = f2u(eb[f]);
+        uint64_t off = 0; /* exclusive prefix sum of record lengths */
+        for (uint64_t b = 0; b < nb; b++) {
+            if (b % OR_SUPER == 0) {
+                sup[2 * (b / OR_SUPER)] = (uint32_t)(off & 0xFFFFFFFFu);
+                sup[2 * (b / OR_SUPER) + 1] = (uint32_t)(off >> 32);
+            }
+            lt[b] = lens[b];
+            memcpy(rec + off, recs[b], 4 * (size_t)lens[b]);
+            off += lens[b];
+        }
+        memcpy(out, w, 4 * total);
+        free(w);
+    }
+    for (uint64_t b = 0; b < nb; b++) free(recs[b]);
+    free(recs);
+    free(lens);
+    return rc;
+}
+
+/* One block's record alone (for spot checks of large streams). */
+int oracle_encode_block(const float *const *x, uint32_t n, uint32_t F, const float *eb, uint32_t K,
+                        uint32_t KF, uint32_t *rec, uint32_t cap_words, uint32_t *rec_words,
+                        uint32_t *perm_out) {
+    if (n == 0 || n > 4096 || F < 1 || F > 64 || KF < 1 || KF > 3 || KF > F || K > 5) return OR_EINVAL;
+    for (uint32_t f = 0; f < F; f++)
+        if (!eb_valid(eb[f])) return OR_EINVAL;
+    block_state st;
+    analyse_block(x, n, F, eb, K, KF, &st);
+    uint32_t need = st.coded_words >= raw_words(n, F) ? raw_words(n, F) : st.coded_words;
+    *rec_words = need;
+    if (need > cap_words) {
+        block_free(&st);
+        return OR_ENOSPC;
+    }
+    uint32_t len = write_block(x, &st, rec);
+    if (perm_out)
+        for (uint32_t p = 0; p < n; p++) perm_out[p] = rec[0] == 1u ? p : st.perm[p];
+    block_free(&st);
+    return (int)(len == need ? OR_OK : OR_EINVAL);
+}
+
+/* Inspection of one block: the intermediate results of stages 1-3.
+ * Arrays are caller-owned: lo[F], s[3], q[F*n], outlier[F*n], key[n],
+ * perm[n], uniq[n], count[n]; widths[2+F] = w_gap, w_cnt, w_f... */
+int oracle_block_trace(const float *const *x, uint32_t n, uint32_t F, const float *eb, uint32_t K,
+                       uint32_t KF, float *lo, uint32_t *s, uint32_t *q, uint8_t *outlier,
+                       uint32_t *key, uint32_t *perm, uint32_t *uniq, uint32_t *count,
+                       uint32_t *widths, uint32_t *U_out, uint32_t *coded_words) {
+    if (n == 0 || F < 1 || F > 64 || KF < 1 || KF > 3 || KF > F || K > 5) return OR_EINVAL;
+    block_state st;
+    analyse_block(x, n, F, eb, K, KF, &st);
+    for (uint32_t f = 0; f < F; f++) lo[f] = st.lo[f];
+    for (uint32_t a = 0; a < 3; a++) s[a] = st.s[a];
+    memcpy(q, st.q, sizeof(uint32_t) * F * n);
+    memcpy(outlier, st.outlier, (size_t)F * n);
+    memcpy(key, st.key, sizeof(uint32_t) * n);
+    memcpy(perm, st.perm, sizeof(uint32_t) * n);
+    memcpy(uniq, st.uniq, sizeof(uint32_t) * st.U);
+    memcpy(count, st.count, sizeof(uint32_t) * st.U);
+    widths[0] = st.w_gap;
+    widths[1] = st.w_cnt;
+    for (uint32_t f = 0; f < F; f++) widths[2 + f] = st.w[f];
+    *U_out = st.U;
+    *coded_words = st.coded_words;
+    block_free(&st);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Decompression (Sec. 3.2): decode, reconstruct, no un-sorting          */
+/* ------------------------------------------------------------------ */
+
+static int decode_block(const uint32_t *rec, uint32_t len, uint32_t n, uint32_t F, uint32_t K,
+                        uint32_t KF, const float *eb, float *const *y, uint64_t base) {
+    if (len < 1) return OR_ECORRUPT;
+    uint32_t mode = rec[0] & 3u;
+    if (mode == 1) {
+        if (rec[0] != 1u || len != raw_words(n, F)) return OR_ECORRUPT;
+        for (uint32_t f = 0; f < F; f++)
+            for (uint32_t i = 0; i < n; i++) y[f][base + i] = u2f(rec[1 + f * n + i]);
+        return OR_OK;
+    }
+    if (mode != 0 || len < 2) return OR_ECORRUPT;
+    uint32_t U = rec[0] >> 2;
+    uint32_t h1 = rec[1];
+    uint32_t w_gap = h1 & 31u, w_cnt = (h1 >> 5) & 31u;
+    uint32_t s[3] = {(h1 >> 10) & 31u, (h1 >> 15) & 31u, (h1 >> 20) & 31u};
+    if ((h1 >> 25) != 0 || U < 1 || U > n || w_gap > 15 || w_cnt > 12) return OR_ECORRUPT;
+    for (uint32_t a = 0; a < 3; a++) {
+        if (a >= KF && s[a] != 0) return OR_ECORRUPT;
+        if (a < KF && s[a] + K > 24) return OR_ECORRUPT;
+    }
+    uint64_t pos = 2;
+    uint64_t need = pos + words_for(U, w_gap) + words_for(U, w_cnt);
+    if (need > len) return OR_ECORRUPT;
+    const uint32_t *gaps = rec + pos;
+    pos += words_for(U, w_gap);
+    const uint32_t *cnts = rec + pos;
+    pos += words_for(U, w_cnt);
+
+    /* Undo delta and run-length coding: the segment ID of every position. */
+    uint32_t *segId = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    int64_t id = -1;
+    uint64_t p = 0;
+    uint64_t idlimit = (uint64_t)1 << (K * KF);
+    for (uint32_t j = 0; j < U; j++) {
+        id = id + (int64_t)get_bits(gaps, (uint64_t)j * w_gap, w_gap) + 1;
+        uint64_t c = (uint64_t)get_bits(cnts, (uint64_t)j * w_cnt, w_cnt) + 1;
+        if ((uint64_t)id >= idlimit || p + c > n) {
+            free(segId);
+            return OR_ECORRUPT;
+        }
+        for (uint64_t k = 0; k < c; k++) segId[p++] = (uint32_t)id;
+    }
+    if (p != n) {
+        free(segId);
+        return OR_ECORRUPT;
+    }
+    for (uint32_t f = 0; f < F; f++) {
+        if (pos + 2 > len) {
+            free(segId);
+            return OR_ECORRUPT;
+        }
+        float lo = u2f(rec[pos]);
+        uint32_t wword = rec[pos + 1];
+        uint32_t w = wword & 31u, nout = wword >> 5;
+        pos += 2;
+        uint32_t wlimit = f < KF ? s[f] : 24;
+        if (w > wlimit || nout > n || pos + words_for(n, w) + 2 * (uint64_t)nout > len) {
+            free(segId);
+            return OR_ECORRUPT;
+        }
+        float twoeb = 2.0f * eb[f];
+        for (uint32_t pp = 0; pp < n; pp++) {
+            uint32_t v = get_bits(rec + pos, (uint64_t)pp * w, w);
+            uint32_t q;
+            if (f < KF) {
+                /* segment ID of axis f, then segId * m + segOffset */
+                uint32_t sid = (segId[pp] >> (K * (KF - 1 - f))) & ((1u << K) - 1u);
+                q = sid * (1u << s[f]) + v;
+            } else {
+                q = v;
+            }
+            y[f][base + pp] = reconstruct(q, twoeb, lo);
+        }
+        pos += words_for(n, w);
+        int64_t last = -1;
+        for (uint32_t k = 0; k < nout; k++) {
+            uint32_t op = rec[pos], bits = rec[pos + 1];
+            pos += 2;
+            if (op >= n || (int64_t)op <= last) {
+                free(segId);
+                return OR_ECORRUPT;
+            }
+            last = op;
+            y[f][base + op] = u2f(bits);
+        }
+    }
+    free(segId);
+    return pos == len ? OR_OK : OR_ECORRUPT;
+}
+
+/* Header fields of a stream (host-side parse). info[0..6] =
+ * N, F, B, K, KF, nblocks, total bytes implied by the tables. */
+int oracle_inspect(const uint8_t *in, uint64_t bytes, uint64_t *info) {
+    if (bytes < 4 * OR_HEADER_WORDS || bytes % 4 != 0) return OR_ECORRUPT;
+    const uint32_t *w = (const uint32_t *)in;
+    if (w[0] != OR_MAGIC || w[1] != OR_VERSION) return OR_ECORRUPT;
+    uint64_t n = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+    uint32_t F = w[4], B = w[5], K = w[6] & 0xFFu, KF = (w[6] >> 8) & 0xFFu;
+    if ((w[6] >> 16) != 0 || !params_valid(F, B, K, KF)) return OR_ECORRUPT;
+    uint64_t nb = nblocks_of(n, B);
+    if (w[7] != (uint32_t)nb || nb > 0xFFFFFFFFull) return OR_ECORRUPT;
+    uint64_t pre = prefix_words(n, F, B);
+    if (4 * pre > bytes) return OR_ECORRUPT;
+    const uint32_t *lt = w + OR_HEADER_WORDS + 2 * nsuper_of(nb) + F;
+    uint64_t total = pre;
+    for (uint64_t b = 0; b < nb; b++) total += lt[b];
+    info[0] = n;
+    info[1] = F;
+    info[2] = B;
+    info[3] = K;
+    info[4] = KF;
+    info[5] = nb;
+    info[6] = 4 * total;
+    return OR_OK;
+}
+
+int oracle_decompress(const uint8_t *in, uint64_t bytes, float *const *out, uint64_t n, uint32_t F) {
+    uint64_t info[7];
+    if (in == NULL) return OR_EINVAL;
+    int rc = oracle_inspect(in, bytes, info);
+    if (rc) return rc;
+    if (info[0] != n || info[1] != F) return OR_EINVAL;
+    if (info[6] != bytes) return OR_ECORRUPT;
+    const uint32_t *w = (const uint32_t *)in;
+    uint32_t B = (uint32_t)info[2], K = (uint32_t)info[3], KF = (uint32_t)info[4];
+    uint64_t nb = info[5], ns = nsuper_of(nb);
+    const uint32_t *sup = w + OR_HEADER_WORDS;
+    const uint32_t *ebt = sup + 2 * ns;
+    const uint32_t *lt = ebt + F;
+    const uint32_t *rec = lt + nb;
+    float eb[64];
+    for (uint32_t f = 0; f < F; f++) {
+        eb[f] = u2f(ebt[f]);
+        if (!eb_valid(eb[f])) return OR_ECORRUPT;
+    }
+    uint64_t off = 0;
+    for (uint64_t b = 0; b < nb; b++) {
+        if (b % OR_SUPER == 0) {
+            uint64_t so = (uint64_t)sup[2 * (b / OR_SUPER)] | ((uint64_t)sup[2 * (b / OR_SUPER) + 1] << 32);
+            if (so != off) return OR_ECORRUPT;
+        }
+        uint32_t nn = (uint32_t)((b + 1) * B <= n ? B : n - b * B);
+        rc = decode_block(rec + off, lt[b], nn, F, K, KF, eb, out, b * B);
+        if (rc) return rc;
+        off += lt[b];
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Error-bound verification and field ranges                            */
+/* ------------------------------------------------------------------ */
+
+/* recon[f][j] is compared with orig[f][perm[j]] (perm NULL: identity).
+ * A pair passes when its bits are identical or |recon - orig| <= eb in
+ * IEEE double.  max_err is over pairs whose difference is a number. */
+int oracle_bound_check(const float *const *orig, const float *const *recon, const uint32_t *perm,
+                       uint64_t n, uint32_t F, const float *eb, uint64_t *violations,
+                       double *max_err) {
+    for (uint32_t f = 0; f < F; f++) {
+        uint64_t v = 0;
+        double m = 0.0;
+        for (uint64_t j = 0; j < n; j++) {
+            float x = orig[f][perm ? perm[j] : j];
+            float y = recon[f][j];
+            double d = fabs((double)y - (double)x);
+            if (!isnan(d) && d > m) m = d;
+            if (f2u(x) != f2u(y) && !(d <= (double)eb[f])) v++;
+        }
+        violations[f] = v;
+        max_err[f] = m;
+    }
+    return OR_OK;
+}
+
+/* Global minimum and maximum of each field over finite values (0, 0 when a
+ * field has none). */
+int oracle_field_range(const float *const *fields, uint64_t n, uint32_t F, float *minmax) {
+    for (uint32_t f = 0; f < F; f++) {
+        int found = 0;
+        float lo = 0.0f, hi = 0.0f;
+        for (uint64_t i = 0; i < n; i++) {
+            float x = fields[f][i];
+            if (!isfinite(x)) continue;
+            if (!found || x < lo) lo = x;
+            if (!found || x > hi) hi = x;
+            found = 1;
+        }
+        minmax[2 * f] = lo;
+        minmax[2 * f + 1] = hi;
+    }
+    return OR_OK;
+}
+
+/* Value-range-relative bound -> absolute bound of one field: rel times the
+ * field's range, rounded to float; a bound that would fall below 2^-120
+ * (a constant field) becomes rel itself, and one above 2^120 is capped. */
+float oracle_rel_to_abs(float rel, float lo, float hi) {
+    float eb = (float)((double)rel * ((double)hi - (double)lo));
+    if (!(eb >= 0x1p-120f)) eb = rel;
+    if (eb > 0x1p120f) eb = 0x1p120f;
+    return eb;
+}

@@ -1,0 +1,376 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test checks the oracle against something the paper or mathematics fixes:
+the Sec. 4.2 worked example, streams derived by hand from the format rules,
+closed forms (constant and on-grid fields), exact rational arithmetic, and
+invariants (error bound, permutation, stream accounting)."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _words(stream):
+    return np.frombuffer(np.ascontiguousarray(stream).tobytes(), dtype="<u4")
+
+
+# ----------------------------------------------------------- worked example
+
+
+def test_sort_rle_worked_example(orc):
+    g = _gold("sort_example.json")
+    seg = [p[0] for p in g["input_pairs"]]
+    off = [p[1] for p in g["input_pairs"]]
+    perm, uniq, cnt, dl = orc.sort_rle(seg)
+    assert [[seg[i], off[i]] for i in perm] == g["sorted_pairs"]
+    assert perm.tolist() == g["perm"]
+    assert uniq.tolist() == g["uniques"]
+    assert cnt.tolist() == g["counts"]
+    assert dl.tolist() == g["deltas"]
+
+
+def test_example_stream_by_hand(orc):
+    g = _gold("example_stream.json")
+    x = np.array(g["x"], np.float32)
+    s, perm = orc.compress([x], g["eb"], B=g["B"], K=g["K"], KF=g["KF"], want_perm=True)
+    assert _words(s).tolist() == g["stream_words"]
+    assert perm.tolist() == g["perm"]
+    y = orc.decompress(s, x.size, 1)[0]
+    assert y.tolist() == g["decompressed"]
+    tr = orc.block_trace([x], g["eb"], K=g["K"], KF=g["KF"])
+    assert tr["s"].tolist() == [1]
+    assert tr["key"].tolist() == [3, 1, 4, 3, 0] * 3
+    assert tr["uniq"].tolist() == [0, 1, 3, 4]
+    assert tr["count"].tolist() == [3, 3, 6, 3]
+
+
+def test_constant_block_by_hand(orc):
+    g = _gold("constant_block.json")
+    x = np.full(4, 3.0, np.float32)
+    s, perm = orc.compress([x], 0.5, B=1024, K=3, KF=1, want_perm=True)
+    assert _words(s).tolist() == g["stream_words"]
+    assert perm.tolist() == [0, 1, 2, 3]
+    tr = orc.block_trace([x], 0.5, K=3, KF=1)
+    assert tr["coded_words"] == len(g["coded_record_words"])
+    y = orc.decompress(s, 4, 1)[0]
+    assert (y == 3.0).all()
+
+
+# ----------------------------------------------------------- closed forms
+
+
+@pytest.mark.parametrize("F", [1, 3, 6])
+@pytest.mark.parametrize("n", [2, 33, 1024])
+def test_constant_field_closed_form(orc, F, n):
+    """Constant fields: grid index 0 everywhere, one run, zero-width payloads.
+    Coded record = 2 + ceil(bw(n-1)/32) + 2F words; reconstruction exact."""
+    c = np.float32(-17.25)
+    xs = [np.full(n, c, np.float32) for _ in range(F)]
+    tr = orc.block_trace(xs, 1e-3)
+    assert tr["U"] == 1 and tr["uniq"].tolist() == [0] and tr["count"].tolist() == [n]
+    assert tr["w_gap"] == 0 and tr["w_cnt"] == int(n - 1).bit_length()
+    assert (tr["w"] == 0).all() and (tr["q"] == 0).all() and not tr["outlier"].any()
+    coded = 2 + (1 if n > 1 else 0) + 2 * F
+    assert tr["coded_words"] == coded
+    s, perm = orc.compress(xs, 1e-3, want_perm=True)
+    w = _words(s)
+    rec_len = min(coded, 1 + F * n)
+    assert s.size == 4 * (8 + 2 + F + 1 + rec_len)
+    ys = orc.decompress(s, n, F)
+    for y in ys:
+        assert (y.view(np.uint32) == np.float32(c).view(np.uint32)).all()
+    assert w[8 + 2 + F] == rec_len
+
+
+def test_on_grid_field_exact(orc):
+    """x = 1 + k * 2^-9 with integer k and eb = 2^-10: every step is exact, so
+    there are no outliers and the decompressed bits equal the input bits at
+    the permuted positions."""
+    rng = np.random.default_rng(7)
+    n = 5000
+    xs = [(1.0 + rng.integers(0, 1000, n) * 2.0 ** -9).astype(np.float32) for _ in range(3)]
+    eb = 2.0 ** -10
+    s, perm = orc.compress(xs, eb, want_perm=True)
+    ys = orc.decompress(s, n, 3)
+    for x, y in zip(xs, ys):
+        assert (y.view(np.uint32) == x[perm].view(np.uint32)).all()
+    for b in range(0, n, 1024):
+        tr = orc.block_trace([x[b:b + 1024] for x in xs], eb)
+        assert not tr["outlier"].any()
+
+
+def test_all_zero_and_negative_zero(orc):
+    x = np.array([0.0, -0.0, 0.0, -0.0] * 40, np.float32)
+    assert np.float32(orc.block_min(x)).view(np.uint32) == 0  # +0.0
+    s, perm = orc.compress([x], 1e-3, want_perm=True)
+    y = orc.decompress(s, x.size, 1)[0]
+    assert (y == 0).all()
+
+
+# ----------------------------------------------------------- block minimum rules
+
+
+def test_block_min_rules(orc):
+    nan, inf = np.float32(np.nan), np.float32(np.inf)
+    assert orc.block_min(np.array([nan, inf, -inf], np.float32)) == 0.0
+    assert orc.block_min(np.array([nan, 5.0, -inf, 2.5, inf], np.float32)) == 2.5
+    v = np.float32(orc.block_min(np.array([-0.0, 1.0], np.float32)))
+    assert v.view(np.uint32) == 0
+    tiny = np.float32(1e-45)  # smallest subnormal
+    assert orc.block_min(np.array([1.0, -tiny, 0.0], np.float32)) == -tiny
+
+
+# ----------------------------------------------------------- quantizer vs exact arithmetic
+
+
+def _round_f32(fr: Fraction) -> float:
+    """Exact round-to-nearest-even of a rational to float32 (normal range)."""
+    if fr == 0:
+        return 0.0
+    sign = -1 if fr < 0 else 1
+    a = abs(fr)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    e = max(e, -126)
+    ulp = Fraction(2) ** (e - 23)
+    m = round(a / ulp)  # Fraction round: ties to even
+    return sign * float(m * ulp)
+
+
+@pytest.mark.parametrize("eb", [2.0 ** -14, 1e-6, 3.3e-5])
+def test_quantizer_against_exact_rationals(orc, eb):
+    """Every float32 in [1, 1 + 2^-10]: the float32 grid index is within 1 of
+    the exact nearest index; a value not flagged as an outlier is
+    reconstructed (exact fma, one rounding) within eb exactly; a flagged value
+    really misses the bound."""
+    eb32 = float(np.float32(eb))
+    lo = 1.0
+    start = np.float32(1.0).view(np.uint32)
+    stop = np.float32(1.0 + 2.0 ** -10).view(np.uint32)
+    xs = np.arange(start, stop + 1, dtype=np.uint32).view(np.float32)
+    twoeb = Fraction(2) * Fraction(eb32)
+    n_out = 0
+    for x in xs[::3]:
+        x = float(x)
+        q, outl = orc.quantize(x, lo, eb32)
+        exact = round((Fraction(x) - Fraction(lo)) / twoeb)
+        assert abs(q - exact) <= 1
+        xr = _round_f32(Fraction(q) * twoeb + Fraction(lo))
+        within = abs(Fraction(xr) - Fraction(x)) <= Fraction(eb32)
+        assert outl == (not within)
+        n_out += outl
+    if eb == 2.0 ** -14:
+        assert n_out == 0  # all arithmetic exact at a power-of-two bound
+
+
+def test_quantizer_range_limit(orc):
+    """Grid indices stop at 2^24 - 1 (32-bit intermediates); beyond, the value
+    is an outlier with index 0."""
+    q, o = orc.quantize(float(2 ** 24 - 1), 0.0, 0.5)
+    assert q == 2 ** 24 - 1 and not o
+    q, o = orc.quantize(float(2 ** 24), 0.0, 0.5)
+    assert q == 0 and o
+    for bad in (np.nan, np.inf, -np.inf):
+        q, o = orc.quantize(float(bad), 0.0, 0.5)
+        assert q == 0 and o
+
+
+def test_mask_equals_modulo():
+    """Table modular_sass: a % 2^s == a & (2^s - 1)."""
+    rng = np.random.default_rng(1)
+    a = rng.integers(0, 2 ** 24, 10000, dtype=np.uint64)
+    for s in range(0, 25):
+        assert ((a % (1 << s)) == (a & ((1 << s) - 1))).all()
+
+
+# ----------------------------------------------------------- invariants
+
+
+def _specials_field(rng, n):
+    x = rng.standard_normal(n).astype(np.float32) * np.float32(10)
+    idx = rng.choice(n, 40, replace=False)
+    specials = np.array([np.nan, np.inf, -np.inf, -0.0, 0.0, 1e-40, -1e-42, 3e38, -3e38,
+                         np.float32(1e-45)], np.float32)
+    x[idx] = specials[rng.integers(0, specials.size, idx.size)]
+    snan = np.array([0x7F800001, 0xFF812345], np.uint32).view(np.float32)
+    x[idx[:2]] = snan
+    return x
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_error_bound_invariant_with_specials(orc, seed):
+    rng = np.random.default_rng(seed)
+    for n, F, eb in [(3000, 3, 1e-3), (1500, 5, 0.25), (2049, 1, 1e-6)]:
+        xs = [_specials_field(rng, n) for _ in range(F)]
+        s, perm = orc.compress(xs, eb, want_perm=True)
+        ys = orc.decompress(s, n, F)
+        for x, y in zip(xs, ys):
+            xo = x[perm]
+            same = xo.view(np.uint32) == y.view(np.uint32)
+            with np.errstate(invalid="ignore"):
+                err = np.abs(y.astype(np.float64) - xo.astype(np.float64))
+            ok = same | (err <= np.float64(np.float32(eb)))
+            assert ok.all()
+            nonfinite = ~np.isfinite(xo)
+            assert same[nonfinite].all()  # non-finite values kept bit-exact
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1023, 1024, 1025, 3000])
+@pytest.mark.parametrize("F", [1, 3, 6])
+def test_edge_sizes_and_accounting(orc, n, F):
+    rng = np.random.default_rng(n + 7 * F)
+    xs = [rng.random(n).astype(np.float32) for _ in range(F)]
+    s, perm = orc.compress(xs, 1e-4, want_perm=True)
+    w = _words(s)
+    nb = (n + 1023) // 1024
+    ns = (nb + 63) // 64
+    info = orc.inspect(s)
+    assert info["n"] == n and info["F"] == F and info["nblocks"] == nb and info["bytes"] == s.size
+    lens = w[8 + 2 * ns + F: 8 + 2 * ns + F + nb].astype(np.int64)
+    assert s.size == 4 * (8 + 2 * ns + F + nb + int(lens.sum()))
+    for b in range(nb):
+        nn = min(1024, n - b * 1024)
+        assert 1 <= lens[b] <= 1 + F * nn
+    assert sorted(perm.tolist()) == list(range(n))
+    for b in range(nb):
+        blk = perm[b * 1024:(b + 1) * 1024]
+        assert ((blk >= b * 1024) & (blk < (b + 1) * 1024)).all()
+    ys = orc.decompress(s, n, F)
+    for x, y in zip(xs, ys):
+        assert (np.abs(y.astype(np.float64) - x[perm].astype(np.float64)) <= np.float32(1e-4)).all()
+
+
+def test_superblock_offsets_are_prefix_sums(orc):
+    rng = np.random.default_rng(3)
+    n = 64 * 1024 * 2 + 5000  # > two superblocks
+    xs = [rng.random(n).astype(np.float32) for _ in range(3)]
+    s, _ = orc.compress(xs, 1e-2)
+    w = _words(s)
+    nb = (n + 1023) // 1024
+    ns = (nb + 63) // 64
+    sup = w[8:8 + 2 * ns].astype(np.uint64)
+    sup = sup[0::2] | (sup[1::2] << np.uint64(32))
+    lens = w[8 + 2 * ns + 3: 8 + 2 * ns + 3 + nb].astype(np.uint64)
+    pref = np.concatenate([[0], np.cumsum(lens)])
+    assert sup.tolist() == [int(pref[64 * j]) for j in range(ns)]
+
+
+def test_sort_is_stable_by_segment(orc):
+    rng = np.random.default_rng(11)
+    pts = [(rng.random(1024) * 0.3).astype(np.float32) for _ in range(3)]
+    tr = orc.block_trace(pts, 1e-3)
+    order = np.argsort(tr["key"], kind="stable")
+    assert (tr["perm"] == order).all()
+    sk = tr["key"][tr["perm"]]
+    assert (np.diff(sk.astype(np.int64)) >= 0).all()
+    assert tr["count"].sum() == 1024
+    assert (np.diff(tr["uniq"].astype(np.int64)) > 0).all()
+    assert tr["U"] <= min(1024, 2 ** 9)
+    # Run-length coding: counts are the histogram of the keys
+    h = np.bincount(tr["key"], minlength=512)
+    assert (h[tr["uniq"]] == tr["count"]).all() and h.sum() == tr["count"].sum()
+
+
+def test_segments_partition_range(orc):
+    """Each key axis is cut into 2^K power-of-two segments covering the
+    block's grid range: segment shift = max(0, bw(qmax) - K)."""
+    rng = np.random.default_rng(5)
+    for K in range(0, 6):
+        pts = [(rng.random(1024) * 10).astype(np.float32) for _ in range(3)]
+        tr = orc.block_trace(pts, 1e-3, K=K)
+        for a in range(3):
+            qmax = int(tr["q"][a].max())
+            seg = tr["q"][a] >> tr["s"][a]
+            assert int(seg.max()) < 2 ** K or (K == 0 and int(seg.max()) == 0)
+            if K >= 1 and qmax >= 2 ** K:
+                assert qmax >> int(tr["s"][a]) >= 2 ** (K - 1)  # top segment in use
+
+
+def test_raw_fallback(orc):
+    """Values that are all outliers (grid range far beyond 2^24) cannot be
+    coded smaller than raw: blocks are stored verbatim, in input order."""
+    rng = np.random.default_rng(9)
+    x = [rng.random(2000).astype(np.float32) for _ in range(2)]
+    eb = 2.0 ** -100
+    s, perm = orc.compress(x, eb, want_perm=True)
+    assert (perm == np.arange(2000)).all()
+    w = _words(s)
+    lens = w[8 + 2 + 2: 8 + 2 + 2 + 2]
+    assert lens.tolist() == [1 + 2 * 1024, 1 + 2 * 976]
+    ys = orc.decompress(s, 2000, 2)
+    for a, b in zip(x, ys):
+        assert (a.view(np.uint32) == b.view(np.uint32)).all()
+
+
+# ----------------------------------------------------------- decoder robustness
+
+
+def test_decoder_rejects_corruption(orc):
+    rng = np.random.default_rng(4)
+    n = 5000
+    xs = [rng.random(n).astype(np.float32) for _ in range(3)]
+    s, _ = orc.compress(xs, 1e-3)
+    assert orc.decompress_status(s, n, 3) == 0
+    assert orc.decompress_status(s[:-4], n, 3) == orc.ECORRUPT
+    bad = s.copy()
+    bad[0] ^= 1
+    assert orc.decompress_status(bad, n, 3) == orc.ECORRUPT
+    bad = s.copy().view(np.uint32)
+    bad[8 + 2 + 3] += 1  # first record length
+    assert orc.decompress_status(bad.view(np.uint8), n, 3) == orc.ECORRUPT
+    assert orc.decompress_status(s, n + 1, 3) == orc.EINVAL
+    # random bit flips in the records: either detected or decoded, never a crash
+    for t in range(200):
+        bad = s.copy()
+        pos = rng.integers(4 * (8 + 2 + 3 + 5), s.size)
+        bad[pos] ^= np.uint8(1 << rng.integers(0, 8))
+        assert orc.decompress_status(bad, n, 3) in (0, orc.ECORRUPT)
+
+
+def test_invalid_parameters(orc):
+    x = [np.zeros(10, np.float32)]
+    for kw in [dict(B=100), dict(B=32), dict(K=6), dict(KF=2)]:
+        with pytest.raises(orc.OracleError):
+            orc.compress(x, 1e-3, **kw)
+    for eb in [0.0, -1.0, np.inf, np.nan, 1e-38, 2.0 ** 121]:
+        with pytest.raises(orc.OracleError):
+            orc.compress(x, eb)
+
+
+# ----------------------------------------------------------- ranges and relative bounds
+
+
+def test_field_range_and_relative_bound(orc):
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(1000).astype(np.float32)
+    x[[3, 9, 77]] = [np.nan, np.inf, -np.inf]
+    mm = orc.field_range([x])
+    fin = x[np.isfinite(x)]
+    assert mm[0, 0] == fin.min() and mm[0, 1] == fin.max()
+    e = orc.rel_to_abs(1e-3, float(mm[0, 0]), float(mm[0, 1]))
+    rel32 = float(np.float32(1e-3))  # the relative bound is a float32 argument
+    assert e == float(np.float32(rel32 * (float(fin.max()) - float(fin.min()))))
+    assert orc.rel_to_abs(1e-3, 5.0, 5.0) == float(np.float32(1e-3))
+
+
+def test_bound_check_counts_violations(orc):
+    x = np.linspace(0, 1, 100).astype(np.float32)
+    y = x.copy()
+    y[5] += np.float32(0.01)
+    y[7] = np.nan
+    v, m = orc.bound_check([x], [y], 1e-3)
+    assert v.tolist() == [2]
+    assert abs(m[0] - abs(float(y[5]) - float(x[5]))) < 1e-12
