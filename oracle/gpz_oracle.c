@@ -717,7 +717,8 @@ int oracle_bound_check(const float *const *orig, const float *const *recon, cons
 }
 
 /* Global minimum and maximum of each field over finite values (0, 0 when a
- * field has none). */
+ * field has none).  A zero extreme is returned as +0.0, so that the result
+ * does not depend on whether -0.0 or +0.0 was met first. */
 int oracle_field_range(const float *const *fields, uint64_t n, uint32_t F, float *minmax) {
     for (uint32_t f = 0; f < F; f++) {
         int found = 0;
@@ -729,6 +730,8 @@ int oracle_field_range(const float *const *fields, uint64_t n, uint32_t F, float
             if (!found || x > hi) hi = x;
             found = 1;
         }
+        if (lo == 0.0f) lo = 0.0f;
+        if (hi == 0.0f) hi = 0.0f;
         minmax[2 * f] = lo;
         minmax[2 * f + 1] = hi;
     }

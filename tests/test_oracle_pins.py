@@ -366,6 +366,13 @@ def test_field_range_and_relative_bound(orc):
     assert orc.rel_to_abs(1e-3, 5.0, 5.0) == float(np.float32(1e-3))
 
 
+def test_field_range_zero_extremes_are_positive(orc):
+    for order in ([-0.0, 0.0], [0.0, -0.0]):
+        x = np.array(order * 3 + [np.nan], np.float32)
+        mm = orc.field_range([x])
+        assert mm.view(np.uint32).tolist() == [[0, 0]]
+
+
 def test_bound_check_counts_violations(orc):
     x = np.linspace(0, 1, 100).astype(np.float32)
     y = x.copy()
