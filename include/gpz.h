@@ -1,0 +1,161 @@
+/*
+ * gpz.h -- C ABI of the MI355X (gfx950) GPZ particle compressor.
+ *
+ * GPZ (arXiv 2508.10305) compresses float32 particle fields under a
+ * per-field absolute error bound: spatial quantization (Sec. 4.1), in-block
+ * sort by segment ID (Sec. 4.2), run-length + delta + fixed-length coding
+ * (Sec. 4.3) and compaction of the block records by a prefix sum of their
+ * sizes (Sec. 4.4).  Decompression reverses the steps without un-sorting
+ * (Sec. 3.2).  The byte layout is "stream format v1" (magic "GPZ1").
+ *
+ * Conventions for every entry point:
+ *  - Pointers prefixed d_ are device pointers, h_ are host pointers.  Field
+ *    arrays are passed as a HOST array of F device pointers (structure of
+ *    arrays, one contiguous float32 array of n values per field).
+ *  - The caller owns every buffer; the library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All work is enqueued on it; calls on distinct streams with distinct
+ *    workspaces may run concurrently.
+ *  - Status codes are returned (gpz_status); nothing throws across the ABI.
+ *    On error the contents of output buffers are unspecified, and nothing
+ *    outside [d_out, d_out + out_capacity) is written.
+ */
+#ifndef GPZ_H
+#define GPZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GPZ_OK = 0,
+    GPZ_EINVAL = -1,      /* bad argument: null pointer, F outside 1..64, bound not a
+                             float in [2^-120, 2^120], bad parameters, workspace too small */
+    GPZ_ENOSPC = -2,      /* output buffer too small; *h_out_bytes holds the size needed */
+    GPZ_ECORRUPT = -3,    /* compressed stream malformed or inconsistent with n / F */
+    GPZ_EDEVICE = -4,     /* a HIP runtime call failed */
+    GPZ_ENOMEM = -5,      /* the library could not allocate a workspace */
+    GPZ_EUNSUPPORTED = -6 /* valid stream/parameters this build has no kernel for */
+} gpz_status;
+
+/* Compression parameters.
+ * block_size : particles per block B, power of two.  The format allows
+ *              64..4096; the gfx950 kernels handle 256, 512, 1024, 2048.
+ *              Default 1024 (32 threads x 32 points per block, Sec. 4.2).
+ * seg_bits   : K, 0..5: each key axis is cut into 2^K power-of-two segments
+ *              (segment size proportional to the block's range, Sec. 4.1).
+ *              Default 3.
+ * key_fields : KF, 1..3 and <= F: the first KF fields are the spatial
+ *              coordinates whose segment IDs form the sort key.  Default
+ *              min(F, 3).
+ */
+typedef struct {
+    uint32_t block_size;
+    uint32_t seg_bits;
+    uint32_t key_fields;
+    uint32_t reserved; /* must be 0 */
+} gpz_params;
+
+/* Fills *p with the defaults for F fields. */
+void gpz_default_params(gpz_params *p, uint32_t nfields);
+
+/* Largest stream gpz_compress can produce for (n, F, p): every block raw.
+ * Returns 0 for invalid parameters. */
+uint64_t gpz_max_compressed_bytes(uint64_t n, uint32_t nfields, const gpz_params *p);
+
+/* Device workspace gpz_compress needs (per-block record slots, sizes,
+ * offsets): about 4*n*F bytes.  Returns 0 for invalid parameters. */
+uint64_t gpz_compress_workspace_bytes(uint64_t n, uint32_t nfields, const gpz_params *p);
+
+/* Device workspace gpz_decompress needs (an error flag). */
+uint64_t gpz_decompress_workspace_bytes(void);
+
+/* Compress n particles x F float32 fields (Sec. 4.1-4.4).
+ *  h_fields     host array of F device pointers, each to n floats.
+ *  h_eb         host array of F absolute error bounds (each in [2^-120, 2^120]).
+ *  p            parameters (NULL = defaults).
+ *  d_out        device buffer of out_capacity bytes for the stream.
+ *  h_out_bytes  receives the stream size in bytes (also on GPZ_ENOSPC).
+ *  d_perm       nullable device array of n uint32: d_perm[j] = input index of
+ *               the particle decompressed at position j (decompression
+ *               keeps the in-block sorted order, Sec. 3.2).
+ *  d_ws/ws_bytes  workspace of at least gpz_compress_workspace_bytes; d_ws ==
+ *               NULL makes the library allocate and free one per call (the
+ *               paper's "end-to-end" setting, Sec. 6.2.2).
+ * Synchronizes `stream` before returning (the size must reach the host). */
+int gpz_compress(const float *const *h_fields, uint64_t n, uint32_t nfields, const float *h_eb,
+                 const gpz_params *p, void *d_out, uint64_t out_capacity, uint64_t *h_out_bytes,
+                 uint32_t *d_perm, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* As gpz_compress, without any host synchronization: the stream size is
+ * written to the device scalar *d_out_bytes.  Requires out_capacity >=
+ * gpz_max_compressed_bytes (so it cannot run out of space) and a caller
+ * workspace.  Safe to capture in a HIP graph. */
+int gpz_compress_async(const float *const *h_fields, uint64_t n, uint32_t nfields,
+                       const float *h_eb, const gpz_params *p, void *d_out, uint64_t out_capacity,
+                       uint64_t *d_out_bytes, uint32_t *d_perm, void *d_ws, uint64_t ws_bytes,
+                       void *stream);
+
+/* Decompress a stream of in_bytes bytes (Sec. 3.2) into F device arrays of n
+ * floats (h_fields_out: host array of F device pointers).  n and F must
+ * match the stream header.  Values come out in in-block sorted order (see
+ * d_perm above).  d_ws: at least gpz_decompress_workspace_bytes (NULL: the
+ * library allocates).  Synchronizes `stream` (to report corruption). */
+int gpz_decompress(const void *d_in, uint64_t in_bytes, float *const *h_fields_out, uint64_t n,
+                   uint32_t nfields, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* As gpz_decompress without host synchronization or header checks against a
+ * host copy: h_header must hold the first 32 + 4*F... bytes of the stream
+ * (at least gpz_header_bytes(n, F, B)); a corrupt record sets
+ * *d_error (device uint32, nonzero) instead of returning GPZ_ECORRUPT. */
+int gpz_decompress_async(const void *d_in, uint64_t in_bytes, float *const *h_fields_out,
+                         uint64_t n, uint32_t nfields, const gpz_params *p, uint32_t *d_error,
+                         void *stream);
+
+/* Error-bound verification: recon[f][j] against orig[f][perm[j]] (d_perm
+ * NULL: identity).  A pair passes when the float bits are equal or
+ * |recon - orig| <= eb in IEEE double.  h_violations[F] receives the failing
+ * pair count, h_max_abs_err[F] the largest |recon - orig| over pairs whose
+ * difference is a number.  Synchronizes `stream`. */
+int gpz_bound_check(const float *const *h_orig, const float *const *h_recon,
+                    const uint32_t *d_perm, uint64_t n, uint32_t nfields, const float *h_eb,
+                    uint64_t *h_violations, double *h_max_abs_err, void *stream);
+
+/* Per-field minimum and maximum over finite values (h_minmax[2F]: min, max;
+ * 0, 0 for a field with none; a zero extreme is returned as +0.0), used to
+ * turn the value-range-relative bounds of the paper's tables into absolute
+ * ones.  Synchronizes `stream`. */
+int gpz_field_range(const float *const *h_fields, uint64_t n, uint32_t nfields, float *h_minmax,
+                    void *stream);
+
+/* Relative bound -> absolute bound of one field: (float)(rel * (hi - lo))
+ * computed in double; below 2^-120 (constant field) it is rel itself; above
+ * 2^120 it is capped. */
+float gpz_rel_to_abs(float rel, float lo, float hi);
+
+/* Header fields parsed from a host copy of the first bytes of a stream.
+ * Returns GPZ_ECORRUPT on a bad magic/version/parameters; needs only the 32
+ * header bytes. */
+typedef struct {
+    uint64_t n;
+    uint32_t nfields, block_size, seg_bits, key_fields;
+    uint64_t nblocks;
+} gpz_info;
+int gpz_inspect(const void *h_prefix, uint64_t bytes, gpz_info *out);
+
+/* Optional per-kernel timing with HIP events on the launch stream.  While
+ * enabled, each gpz_compress / gpz_decompress call records events around
+ * its kernels; gpz_last_timing returns the durations (ms) of the most recent
+ * call on this thread: [0] encode, [1] scan, [2] compact copy (compress) or
+ * [0] decode (decompress); count in *n. */
+int gpz_set_timing(int enable);
+int gpz_last_timing(float *ms, int max, int *n);
+
+const char *gpz_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPZ_H */

@@ -1,0 +1,445 @@
+// C ABI of libgpz (declared in include/gpz.h): argument checks, workspace
+// layout, kernel sequencing and status reporting.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "gpz.h"
+#include "gpz_internal.h"
+
+using namespace gpz;
+
+namespace {
+
+thread_local bool g_timing = false;
+thread_local float g_times[4];
+thread_local int g_ntimes = 0;
+
+struct Timer {
+    hipEvent_t ev[5];
+    int n = 0;
+    bool on;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : on(g_timing), s(st) {
+        if (on)
+            for (int i = 0; i < 5; i++)
+                if (hipEventCreate(&ev[i]) != hipSuccess) on = false;
+    }
+    void mark() {
+        if (on && n < 5) (void)hipEventRecord(ev[n++], s);
+    }
+    void finish() {  // call after the stream has been synchronized
+        if (!on) return;
+        g_ntimes = 0;
+        for (int i = 0; i + 1 < n; i++) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            g_times[g_ntimes++] = ms;
+        }
+    }
+    ~Timer() {
+        if (on)
+            for (int i = 0; i < 5; i++) (void)hipEventDestroy(ev[i]);
+    }
+};
+
+bool eb_valid(float eb) { return isfinite(eb) && eb >= 0x1p-120f && eb <= 0x1p120f; }
+
+bool params_ok(uint32_t F, const gpz_params& p) {
+    if (F < 1 || F > kMaxFields) return false;
+    uint32_t B = p.block_size;
+    if (B < 64 || B > 4096 || (B & (B - 1)) != 0) return false;
+    if (p.key_fields < 1 || p.key_fields > 3 || p.key_fields > F) return false;
+    if (p.seg_bits > 5 || p.reserved != 0) return false;
+    return true;
+}
+
+bool kernel_block_size(uint32_t B) { return B == 256 || B == 512 || B == 1024 || B == 2048; }
+
+gpz_params resolve(const gpz_params* p, uint32_t F) {
+    gpz_params q;
+    gpz_default_params(&q, F);
+    if (p) q = *p;
+    return q;
+}
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+struct CompressWs {
+    uint32_t* temp;
+    uint32_t* lens;
+    uint64_t* offs;
+    uint64_t* total;
+    uint32_t slot_words;
+    uint64_t bytes;
+};
+
+CompressWs layout(uint64_t n, uint32_t F, uint32_t B, char* base) {
+    CompressWs w{};
+    uint64_t nb = nblocks_of(n, B);
+    w.slot_words = (uint32_t)((1 + (uint64_t)F * B + 3) & ~uint64_t(3));
+    uint64_t o = 0;
+    w.temp = reinterpret_cast<uint32_t*>(base + o);
+    o = align256(o + nb * w.slot_words * 4ull);
+    w.lens = reinterpret_cast<uint32_t*>(base + o);
+    o = align256(o + nb * 4ull);
+    w.offs = reinterpret_cast<uint64_t*>(base + o);
+    o = align256(o + nb * 8ull);
+    w.total = reinterpret_cast<uint64_t*>(base + o);
+    o = align256(o + 64);
+    w.bytes = o;
+    return w;
+}
+
+int to_status(hipError_t e) { return e == hipSuccess ? GPZ_OK : GPZ_EDEVICE; }
+
+// Shared body of gpz_compress / gpz_compress_async.
+int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const float* h_eb,
+                  const gpz_params* pp, void* d_out, uint64_t cap, uint64_t* h_out_bytes,
+                  uint64_t* d_out_bytes, uint32_t* d_perm, void* d_ws, uint64_t ws_bytes,
+                  hipStream_t s, bool sync) {
+    if (F < 1 || F > kMaxFields || !h_eb) return GPZ_EINVAL;
+    gpz_params p = resolve(pp, F);
+    if (!params_ok(F, p)) return GPZ_EINVAL;
+    if (!kernel_block_size(p.block_size)) return GPZ_EUNSUPPORTED;
+    if (n > 0 && !h_fields) return GPZ_EINVAL;
+    if (!d_out) return GPZ_EINVAL;
+    if (n > ((uint64_t)1 << 32) * p.block_size) return GPZ_EINVAL;  // block count fits 32 bits
+    for (uint32_t f = 0; f < F; f++) {
+        if (!eb_valid(h_eb[f])) return GPZ_EINVAL;
+        if (n > 0 && !h_fields[f]) return GPZ_EINVAL;
+    }
+    const uint32_t B = p.block_size;
+    const uint64_t nb = nblocks_of(n, B);
+    CompressWs probe = layout(n, F, B, nullptr);
+    char* ws = static_cast<char*>(d_ws);
+    bool owned = false;
+    if (!ws) {
+        if (!sync) return GPZ_EINVAL;
+        if (getenv("GPZ_FAULT") && strcmp(getenv("GPZ_FAULT"), "alloc") == 0) return GPZ_ENOMEM;
+        if (hipMalloc(&ws, probe.bytes) != hipSuccess) return GPZ_ENOMEM;
+        owned = true;
+    } else if (ws_bytes < probe.bytes) {
+        return GPZ_EINVAL;
+    }
+    CompressWs w = layout(n, F, B, ws);
+
+    EncodeArgs ea{};
+    CopyArgs ca{};
+    for (uint32_t f = 0; f < F; f++) {
+        ea.x[f] = n ? h_fields[f] : nullptr;
+        ea.eb[f] = h_eb[f];
+        ea.twoeb[f] = 2.0f * h_eb[f];
+        ea.inv[f] = 1.0f / ea.twoeb[f];
+        uint32_t bits;
+        memcpy(&bits, &h_eb[f], 4);
+        ca.eb_bits[f] = bits;
+    }
+    ea.n = n;
+    ea.F = F;
+    ea.K = p.seg_bits;
+    ea.KF = p.key_fields;
+    ea.B = B;
+    ea.nblocks = (uint32_t)nb;
+    ea.slot_words = w.slot_words;
+    ea.temp = w.temp;
+    ea.lens = w.lens;
+    ea.perm = d_perm;
+
+    ScanArgs sa{};
+    sa.lens = w.lens;
+    sa.offs = w.offs;
+    sa.total_bytes = w.total;
+    sa.ext_bytes = d_out_bytes;
+    sa.nblocks = (uint32_t)nb;
+    sa.prefix = prefix_words(n, F, B);
+
+    ca.temp = w.temp;
+    ca.lens = w.lens;
+    ca.offs = w.offs;
+    ca.total_bytes = w.total;
+    ca.out = static_cast<uint32_t*>(d_out);
+    ca.capacity = cap;
+    ca.slot_words = w.slot_words;
+    ca.nblocks = (uint32_t)nb;
+    ca.n = n;
+    ca.F = F;
+    ca.B = B;
+    ca.K = p.seg_bits;
+    ca.KF = p.key_fields;
+
+    Timer tm(s);
+    int rc = GPZ_OK;
+    tm.mark();
+    if (rc == GPZ_OK) rc = to_status(launch_encode(ea, s));
+    tm.mark();
+    if (rc == GPZ_OK) rc = to_status(launch_scan(sa, s));
+    tm.mark();
+    if (rc == GPZ_OK) rc = to_status(launch_copy(ca, s));
+    tm.mark();
+    if (sync) {
+        uint64_t total = 0;
+        if (rc == GPZ_OK) rc = to_status(hipMemcpyAsync(&total, w.total, 8, hipMemcpyDeviceToHost, s));
+        if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+        tm.finish();
+        if (h_out_bytes) *h_out_bytes = total;
+        if (rc == GPZ_OK && total > cap) rc = GPZ_ENOSPC;
+    }
+    if (owned) (void)hipFree(ws);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gpz_default_params(gpz_params* p, uint32_t nfields) {
+    if (!p) return;
+    p->block_size = 1024;
+    p->seg_bits = 3;
+    p->key_fields = nfields < 3 ? (nfields ? nfields : 1) : 3;
+    p->reserved = 0;
+}
+
+uint64_t gpz_max_compressed_bytes(uint64_t n, uint32_t nfields, const gpz_params* pp) {
+    gpz_params p = resolve(pp, nfields);
+    if (!params_ok(nfields, p)) return 0;
+    uint64_t nb = nblocks_of(n, p.block_size);
+    return 4 * (prefix_words(n, nfields, p.block_size) + nb + (uint64_t)nfields * n);
+}
+
+uint64_t gpz_compress_workspace_bytes(uint64_t n, uint32_t nfields, const gpz_params* pp) {
+    gpz_params p = resolve(pp, nfields);
+    if (!params_ok(nfields, p)) return 0;
+    return layout(n, nfields, p.block_size, nullptr).bytes;
+}
+
+uint64_t gpz_decompress_workspace_bytes(void) { return 256; }
+
+int gpz_compress(const float* const* h_fields, uint64_t n, uint32_t nfields, const float* h_eb,
+                 const gpz_params* p, void* d_out, uint64_t out_capacity, uint64_t* h_out_bytes,
+                 uint32_t* d_perm, void* d_ws, uint64_t ws_bytes, void* stream) {
+    return compress_impl(h_fields, n, nfields, h_eb, p, d_out, out_capacity, h_out_bytes, nullptr,
+                         d_perm, d_ws, ws_bytes, static_cast<hipStream_t>(stream), true);
+}
+
+int gpz_compress_async(const float* const* h_fields, uint64_t n, uint32_t nfields,
+                       const float* h_eb, const gpz_params* p, void* d_out, uint64_t out_capacity,
+                       uint64_t* d_out_bytes, uint32_t* d_perm, void* d_ws, uint64_t ws_bytes,
+                       void* stream) {
+    if (!d_out_bytes || !d_ws) return GPZ_EINVAL;
+    uint64_t need = gpz_max_compressed_bytes(n, nfields, p);
+    if (need == 0 || out_capacity < need) return GPZ_EINVAL;
+    return compress_impl(h_fields, n, nfields, h_eb, p, d_out, out_capacity, nullptr, d_out_bytes,
+                         d_perm, d_ws, ws_bytes, static_cast<hipStream_t>(stream), false);
+}
+
+static int decompress_impl(const void* d_in, uint64_t in_bytes, float* const* h_out, uint64_t n,
+                           uint32_t F, const gpz_params& p, uint32_t* d_err, hipStream_t s,
+                           Timer* tm) {
+    const uint32_t B = p.block_size;
+    const uint64_t nb = nblocks_of(n, B);
+    const uint64_t pre = prefix_words(n, F, B);
+    if (in_bytes % 4 != 0 || in_bytes < 4 * pre) return GPZ_ECORRUPT;
+    if (nb == 0) {
+        // nothing to decode; the stream is the header and the eb table
+        if (in_bytes != 4 * pre) return GPZ_ECORRUPT;
+        std::vector<uint32_t> h(pre);
+        if (hipMemcpyAsync(h.data(), d_in, 4 * pre, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return GPZ_EDEVICE;
+        for (uint32_t f = 0; f < F; f++) {
+            float e;
+            memcpy(&e, &h[kHeaderWords + f], 4);
+            if (!eb_valid(e)) return GPZ_ECORRUPT;
+        }
+    }
+    DecodeArgs da{};
+    da.in = static_cast<const uint32_t*>(d_in);
+    da.in_words = in_bytes / 4;
+    for (uint32_t f = 0; f < F; f++) da.y[f] = n ? h_out[f] : nullptr;
+    da.n = n;
+    da.F = F;
+    da.K = p.seg_bits;
+    da.KF = p.key_fields;
+    da.B = B;
+    da.nblocks = (uint32_t)nb;
+    da.prefix = pre;
+    da.err = d_err;
+    int rc = to_status(launch_fill_u32(d_err, 0u, 1, s));
+    if (tm) tm->mark();
+    if (rc == GPZ_OK) rc = to_status(launch_decode(da, s));
+    if (tm) tm->mark();
+    return rc;
+}
+
+int gpz_decompress(const void* d_in, uint64_t in_bytes, float* const* h_fields_out, uint64_t n,
+                   uint32_t nfields, void* d_ws, uint64_t ws_bytes, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!d_in || nfields < 1 || nfields > kMaxFields) return GPZ_EINVAL;
+    if (n > 0 && !h_fields_out) return GPZ_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < nfields; f++)
+        if (!h_fields_out[f]) return GPZ_EINVAL;
+    if (in_bytes < 4 * kHeaderWords) return GPZ_ECORRUPT;
+    uint32_t hdr[kHeaderWords];
+    if (hipMemcpyAsync(hdr, d_in, sizeof(hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return GPZ_EDEVICE;
+    gpz_info info;
+    int rc = gpz_inspect(hdr, sizeof(hdr), &info);
+    if (rc) return rc;
+    if (info.n != n || info.nfields != nfields) return GPZ_EINVAL;
+    if (!kernel_block_size(info.block_size)) return GPZ_EUNSUPPORTED;
+    gpz_params p{info.block_size, info.seg_bits, info.key_fields, 0};
+    uint32_t* err = static_cast<uint32_t*>(d_ws);
+    bool owned = false;
+    if (!err) {
+        if (hipMalloc(&err, 256) != hipSuccess) return GPZ_ENOMEM;
+        owned = true;
+    } else if (ws_bytes < gpz_decompress_workspace_bytes()) {
+        return GPZ_EINVAL;
+    }
+    Timer tm(s);
+    rc = decompress_impl(d_in, in_bytes, h_fields_out, n, nfields, p, err, s, &tm);
+    uint32_t e = 0;
+    if (rc == GPZ_OK) rc = to_status(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s));
+    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    tm.finish();
+    if (owned) (void)hipFree(err);
+    if (rc == GPZ_OK && e) rc = GPZ_ECORRUPT;
+    return rc;
+}
+
+int gpz_decompress_async(const void* d_in, uint64_t in_bytes, float* const* h_fields_out,
+                         uint64_t n, uint32_t nfields, const gpz_params* pp, uint32_t* d_error,
+                         void* stream) {
+    if (!d_in || !d_error || nfields < 1 || nfields > kMaxFields) return GPZ_EINVAL;
+    if (n > 0 && !h_fields_out) return GPZ_EINVAL;
+    gpz_params p = resolve(pp, nfields);
+    if (!params_ok(nfields, p)) return GPZ_EINVAL;
+    if (!kernel_block_size(p.block_size)) return GPZ_EUNSUPPORTED;
+    return decompress_impl(d_in, in_bytes, h_fields_out, n, nfields, p, d_error,
+                           static_cast<hipStream_t>(stream), nullptr);
+}
+
+int gpz_bound_check(const float* const* h_orig, const float* const* h_recon,
+                    const uint32_t* d_perm, uint64_t n, uint32_t nfields, const float* h_eb,
+                    uint64_t* h_violations, double* h_max_abs_err, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nfields < 1 || nfields > kMaxFields || !h_eb || !h_violations || !h_max_abs_err)
+        return GPZ_EINVAL;
+    if (n > 0 && (!h_orig || !h_recon)) return GPZ_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < nfields; f++)
+        if (!h_orig[f] || !h_recon[f]) return GPZ_EINVAL;
+    unsigned long long* acc = nullptr;
+    if (hipMalloc(&acc, 16ull * nfields) != hipSuccess) return GPZ_ENOMEM;
+    int rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, 4ull * nfields, s));
+    if (rc == GPZ_OK && n > 0)
+        rc = to_status(launch_bound_check(h_orig, h_recon, d_perm, n, nfields, h_eb, acc,
+                                          acc + nfields, s));
+    std::vector<unsigned long long> h(2 * nfields);
+    if (rc == GPZ_OK)
+        rc = to_status(hipMemcpyAsync(h.data(), acc, 16ull * nfields, hipMemcpyDeviceToHost, s));
+    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    (void)hipFree(acc);
+    if (rc) return rc;
+    for (uint32_t f = 0; f < nfields; f++) {
+        h_violations[f] = h[f];
+        double d;
+        memcpy(&d, &h[nfields + f], 8);
+        h_max_abs_err[f] = d;
+    }
+    return GPZ_OK;
+}
+
+int gpz_field_range(const float* const* h_fields, uint64_t n, uint32_t nfields, float* h_minmax,
+                    void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nfields < 1 || nfields > kMaxFields || !h_minmax) return GPZ_EINVAL;
+    if (n > 0 && !h_fields) return GPZ_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < nfields; f++)
+        if (!h_fields[f]) return GPZ_EINVAL;
+    int* keys = nullptr;
+    if (hipMalloc(&keys, 8ull * nfields) != hipSuccess) return GPZ_ENOMEM;
+    int rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(keys), 0x7FFFFFFFu, nfields, s));
+    if (rc == GPZ_OK)
+        rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(keys) + nfields, 0x80000000u,
+                                       nfields, s));
+    if (rc == GPZ_OK && n > 0) rc = to_status(launch_field_range(h_fields, n, nfields, keys, s));
+    std::vector<int> h(2 * nfields);
+    if (rc == GPZ_OK)
+        rc = to_status(hipMemcpyAsync(h.data(), keys, 8ull * nfields, hipMemcpyDeviceToHost, s));
+    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    (void)hipFree(keys);
+    if (rc) return rc;
+    for (uint32_t f = 0; f < nfields; f++) {
+        int mn = h[f], mx = h[nfields + f];
+        float lo = 0.0f, hi = 0.0f;
+        if (mn <= mx) {  // some finite value was seen
+            int a = mn ^ ((mn >> 31) & 0x7FFFFFFF), b = mx ^ ((mx >> 31) & 0x7FFFFFFF);
+            memcpy(&lo, &a, 4);
+            memcpy(&hi, &b, 4);
+            if (lo == 0.0f) lo = 0.0f;
+            if (hi == 0.0f) hi = 0.0f;
+        }
+        h_minmax[2 * f] = lo;
+        h_minmax[2 * f + 1] = hi;
+    }
+    return GPZ_OK;
+}
+
+float gpz_rel_to_abs(float rel, float lo, float hi) {
+    float eb = (float)((double)rel * ((double)hi - (double)lo));
+    if (!(eb >= 0x1p-120f)) eb = rel;
+    if (eb > 0x1p120f) eb = 0x1p120f;
+    return eb;
+}
+
+int gpz_inspect(const void* h_prefix, uint64_t bytes, gpz_info* out) {
+    if (!h_prefix || !out) return GPZ_EINVAL;
+    if (bytes < 4 * kHeaderWords) return GPZ_ECORRUPT;
+    uint32_t w[kHeaderWords];
+    memcpy(w, h_prefix, sizeof(w));
+    if (w[0] != kMagic || w[1] != kVersion) return GPZ_ECORRUPT;
+    gpz_params p{w[5], w[6] & 0xFFu, (w[6] >> 8) & 0xFFu, 0};
+    if ((w[6] >> 16) != 0 || !params_ok(w[4], p)) return GPZ_ECORRUPT;
+    uint64_t n = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+    uint64_t nb = nblocks_of(n, p.block_size);
+    if (nb > 0xFFFFFFFFull || w[7] != (uint32_t)nb) return GPZ_ECORRUPT;
+    out->n = n;
+    out->nfields = w[4];
+    out->block_size = p.block_size;
+    out->seg_bits = p.seg_bits;
+    out->key_fields = p.key_fields;
+    out->nblocks = nb;
+    return GPZ_OK;
+}
+
+int gpz_set_timing(int enable) {
+    g_timing = enable != 0;
+    return GPZ_OK;
+}
+
+int gpz_last_timing(float* ms, int max, int* n) {
+    if (!ms || !n) return GPZ_EINVAL;
+    int k = g_ntimes < max ? g_ntimes : max;
+    for (int i = 0; i < k; i++) ms[i] = g_times[i];
+    *n = k;
+    return GPZ_OK;
+}
+
+const char* gpz_strerror(int status) {
+    switch (status) {
+        case GPZ_OK: return "ok";
+        case GPZ_EINVAL: return "invalid argument";
+        case GPZ_ENOSPC: return "output buffer too small";
+        case GPZ_ECORRUPT: return "corrupt or inconsistent stream";
+        case GPZ_EDEVICE: return "HIP runtime error";
+        case GPZ_ENOMEM: return "workspace allocation failed";
+        case GPZ_EUNSUPPORTED: return "block size without a gfx950 kernel";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

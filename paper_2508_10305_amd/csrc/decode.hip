@@ -1,0 +1,259 @@
+// Block decoder (Sec. 3.2: decompression reverses the compression steps,
+// without un-sorting): one wave64 per block locates its record through the
+// superblock table, undoes the delta and run-length coding of the segment
+// IDs, unpacks the fixed-length payloads, rebuilds every value with
+// fma(q, 2eb, lo), patches outliers and stores the block in sorted order.
+// Every read of the record is checked against its length first; a malformed
+// record sets the error flag and the block is skipped.
+#include "gpz_internal.h"
+
+namespace gpz {
+namespace {
+
+template <int ITEMS>
+__device__ __forceinline__ uint32_t pad_addr(uint32_t p) {
+    return p + 4 * (p / ITEMS);
+}
+
+// Value i of a fixed-length array of width w (bits [i*w, i*w+w)).
+__device__ __forceinline__ uint32_t unpack_one(const uint32_t* __restrict__ arr, uint32_t i,
+                                               uint32_t w) {
+    if (w == 0) return 0u;
+    uint32_t bit = i * w;
+    uint32_t wd = bit >> 5, sh = bit & 31u;
+    uint32_t v = arr[wd] >> sh;
+    if (sh + w > 32u) v |= arr[wd + 1] << (32u - sh);
+    return w == 32u ? v : (v & ((1u << w) - 1u));
+}
+
+__device__ __forceinline__ bool eb_ok(float eb) {
+    return __builtin_isfinite(eb) && eb >= 0x1p-120f && eb <= 0x1p120f;
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void store_block(float* __restrict__ y, uint64_t base, uint32_t nb,
+                                            uint32_t lane, const uint32_t* stage) {
+    float* p = y + base + (uint64_t)lane * ITEMS;
+    const uint32_t* src = stage + lane * (ITEMS + 4);
+    const bool full = (lane + 1) * ITEMS <= nb;
+    if (full && ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)) {
+        const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+        u32x4* p4 = reinterpret_cast<u32x4*>(p);
+#pragma unroll
+        for (int k = 0; k < ITEMS / 4; k++) __builtin_nontemporal_store(s4[k], p4 + k);
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++)
+            if (lane * ITEMS + j < nb) p[j] = u2f(src[j]);
+    }
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
+    constexpr uint32_t B = 64 * ITEMS;
+    constexpr uint32_t kStageWords = 64 * (ITEMS + 4);
+    __shared__ __align__(16) uint32_t stage[kStageWords];
+
+    const uint32_t lane = threadIdx.x;
+    const uint32_t b = blockIdx.x;
+    const uint64_t base = (uint64_t)b * B;
+    const uint32_t nb = (uint32_t)((a.n - base) < B ? (a.n - base) : B);
+    const uint32_t F = a.F, K = a.K, KF = a.KF;
+    const uint64_t nsup = nsuper_of(a.nblocks);
+    const uint32_t* sup = a.in + kHeaderWords;
+    const uint32_t* ebt = sup + 2 * nsup;
+    const uint32_t* lens = ebt + F;
+    const uint32_t* recs = a.in + a.prefix;
+    const uint64_t rec_total = a.in_words - a.prefix;
+
+    // ---- locate the record: superblock offset + lengths before it
+    const uint32_t sb = b / kSuper;
+    const uint32_t first = sb * kSuper;
+    uint32_t mine = (first + lane < b) ? lens[first + lane] : 0u;
+    uint64_t off = ((uint64_t)sup[2 * sb] | ((uint64_t)sup[2 * sb + 1] << 32)) + wave_sum_u32(mine);
+    const uint32_t len = lens[b];
+    bool bad = off + len > rec_total;
+    if (b == 0 && (sup[0] | sup[1]) != 0u) bad = true;
+    if (b + 1 == a.nblocks && off + len != rec_total) bad = true;
+    for (uint32_t f = lane; f < F; f += 64)
+        if (!eb_ok(u2f(ebt[f]))) bad = true;
+    bad = __any(bad);
+    if (b == first && sb > 0) {
+        // consistency of this superblock's offset with the previous one
+        uint32_t pl = lens[first - kSuper + lane];
+        uint64_t prev = ((uint64_t)sup[2 * sb - 2] | ((uint64_t)sup[2 * sb - 1] << 32));
+        if (prev + wave_sum_u32(pl) != off) bad = true;
+    }
+    if (bad) {
+        if (lane == 0) *a.err = 1u;
+        return;
+    }
+    const uint32_t* rec = recs + off;
+    const uint32_t h0 = len ? rec[0] : 0u;
+    const uint32_t mode = h0 & 3u;
+
+    if (len == 0 || mode > 1) {
+        if (lane == 0) *a.err = 1u;
+        return;
+    }
+    if (mode == 1) {
+        if (h0 != 1u || len != 1 + F * nb) {
+            if (lane == 0) *a.err = 1u;
+            return;
+        }
+        for (uint32_t f = 0; f < F; f++) {
+            float* yf = a.y[f] + base;
+            const uint32_t* src = rec + 1 + f * nb;
+            for (uint32_t i = lane; i < nb; i += 64) yf[i] = u2f(src[i]);
+        }
+        return;
+    }
+
+    // ---- coded record header
+    const uint32_t U = h0 >> 2;
+    const uint32_t h1 = len > 1 ? rec[1] : 0xFFFFFFFFu;
+    const uint32_t w_gap = h1 & 31u, w_cnt = (h1 >> 5) & 31u;
+    const uint32_t s0 = (h1 >> 10) & 31u, s1 = (h1 >> 15) & 31u, s2 = (h1 >> 20) & 31u;
+    bad = len < 2 || (h1 >> 25) != 0u || U < 1 || U > nb || w_gap > 15 || w_cnt > 12;
+    bad |= (KF < 2 && s1 != 0) || (KF < 3 && s2 != 0);
+    bad |= (s0 + K > 24) || (KF > 1 && s1 + K > 24) || (KF > 2 && s2 + K > 24);
+    const uint32_t gw = words_for(U, w_gap), cw = words_for(U, w_cnt);
+    bad |= (uint64_t)2 + gw + cw > len;
+    if (bad) {
+        if (lane == 0) *a.err = 1u;
+        return;
+    }
+
+    // ---- undo delta + run-length coding (Sec. 4.3)
+    uint32_t g1[ITEMS], c1[ITEMS];
+    uint32_t gs = 0, cs = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        uint32_t i = lane * ITEMS + j;
+        g1[j] = i < U ? unpack_one(rec + 2, i, w_gap) + 1u : 0u;
+        c1[j] = i < U ? unpack_one(rec + 2 + gw, i, w_cnt) + 1u : 0u;
+        gs += g1[j];
+        cs += c1[j];
+    }
+    const uint32_t gincl = wave_incl_scan_u32(gs), cincl = wave_incl_scan_u32(cs);
+    const uint32_t gtot = (uint32_t)__shfl((int)gincl, 63), ctot = (uint32_t)__shfl((int)cincl, 63);
+    // largest ID = sum(gap+1) - 1 must fit K*KF bits; run lengths sum to nb
+    if (ctot != nb || gtot == 0 || gtot - 1u >= (1u << (K * KF))) {
+        if (lane == 0) *a.err = 1u;
+        return;
+    }
+    // mark run starts: stage[start] = ID (IDs increase, so a prefix maximum
+    // over positions recovers the ID of every position)
+    for (uint32_t p = lane; p < nb; p += 64) stage[pad_addr<ITEMS>(p)] = 0u;
+    __syncthreads();
+    {
+        uint32_t u = gincl - gs, st = cincl - cs;
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t i = lane * ITEMS + j;
+            if (i < U) {
+                u += g1[j];
+                stage[pad_addr<ITEMS>(st)] = u - 1u;
+                st += c1[j];
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t key[ITEMS];
+    {
+        uint32_t run = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t p = lane * ITEMS + j;
+            uint32_t v = p < nb ? stage[pad_addr<ITEMS>(p)] : 0u;
+            run = max(run, v);
+            key[j] = run;
+        }
+        uint32_t carry = wave_incl_max_u32(run);
+        carry = (uint32_t)__shfl_up((int)carry, 1);
+        if (lane == 0) carry = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) key[j] = max(key[j], carry);
+    }
+    __syncthreads();
+
+    // ---- fields
+    uint64_t pos = 2 + gw + cw;
+    for (uint32_t f = 0; f < F; f++) {
+        if (pos + 2 > len) {
+            bad = true;
+            break;
+        }
+        const float lo = u2f(rec[pos]);
+        const uint32_t wn = rec[pos + 1];
+        const uint32_t w = wn & 31u, nout = wn >> 5;
+        uint32_t s = 0, shift = 0;
+        if (f < KF) {
+            s = f == 0 ? s0 : (f == 1 ? s1 : s2);
+            shift = K * (KF - 1 - f);
+        }
+        const uint32_t wlim = f < KF ? s : 24u;
+        const uint32_t pw = words_for(nb, w);
+        if (w > wlim || nout > nb || pos + 2 + pw + 2 * (uint64_t)nout > len) {
+            bad = true;
+            break;
+        }
+        const float eb = u2f(ebt[f]);
+        if (!eb_ok(eb)) {
+            bad = true;
+            break;
+        }
+        const float twoeb = 2.0f * eb;
+        const uint32_t* pay = rec + pos + 2;
+        const uint32_t kmask = (1u << K) - 1u;
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t p = lane * ITEMS + j;
+            if (p < nb) {
+                uint32_t v = unpack_one(pay, p, w);
+                uint32_t q = f < KF ? ((((key[j] >> shift) & kmask) << s) | v) : v;
+                stage[pad_addr<ITEMS>(p)] = f2u(__builtin_fmaf((float)q, twoeb, lo));
+            }
+        }
+        __syncthreads();
+        const uint32_t* ol = pay + pw;
+        bool obad = false;
+        for (uint32_t k = lane; k < nout; k += 64) {
+            uint32_t op = ol[2 * k];
+            uint32_t prevp = k ? ol[2 * k - 2] : 0u;
+            if (op >= nb || (k && prevp >= op)) {
+                obad = true;
+            } else {
+                stage[pad_addr<ITEMS>(op)] = ol[2 * k + 1];
+            }
+        }
+        if (__any(obad)) {
+            bad = true;
+            break;
+        }
+        __syncthreads();
+        store_block<ITEMS>(a.y[f], base, nb, lane, stage);
+        __syncthreads();
+        pos += 2 + pw + 2 * (uint64_t)nout;
+    }
+    if (bad || pos != len) {
+        if (lane == 0) *a.err = 1u;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t s) {
+    if (a.nblocks == 0) return hipSuccess;
+    dim3 grid(a.nblocks), block(64);
+    switch (a.B) {
+        case 256: hipLaunchKernelGGL(decode_blocks<4>, grid, block, 0, s, a); break;
+        case 512: hipLaunchKernelGGL(decode_blocks<8>, grid, block, 0, s, a); break;
+        case 1024: hipLaunchKernelGGL(decode_blocks<16>, grid, block, 0, s, a); break;
+        case 2048: hipLaunchKernelGGL(decode_blocks<32>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gpz

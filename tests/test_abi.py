@@ -1,0 +1,94 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and its host-side helpers and argument checks behave (no GPU work)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpz.h")
+
+
+@pytest.fixture(scope="module")
+def gpz():
+    import paper_2508_10305_amd as g
+    if not os.path.exists(g.LIB_PATH):
+        from paper_2508_10305_amd import build
+        build.build_lib()
+    return g
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpz_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("gpz_compress", "gpz_decompress", "gpz_bound_check"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(gpz):
+    L = gpz.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) == set(gpz.EXPORTS)
+
+
+def test_sizes_match_oracle(gpz, orc):
+    for n in [0, 1, 1023, 1024, 1025, 10 ** 6]:
+        for F in [1, 3, 6]:
+            assert gpz.max_compressed_bytes(n, F) == orc.max_bytes(n, F, 1024)
+    assert gpz.compress_workspace_bytes(10 ** 6, 3) >= 4 * 3 * 10 ** 6
+
+
+def test_rel_to_abs_matches_oracle(gpz, orc):
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        lo, hi = sorted(rng.standard_normal(2) * 10.0 ** rng.integers(-3, 6))
+        lo, hi = float(np.float32(lo)), float(np.float32(hi))
+        for rel in (1e-2, 1e-3, 1e-4):
+            assert gpz.rel_to_abs(rel, lo, hi) == orc.rel_to_abs(rel, lo, hi)
+    assert gpz.rel_to_abs(1e-3, 2.0, 2.0) == orc.rel_to_abs(1e-3, 2.0, 2.0)
+
+
+def test_inspect_parses_oracle_stream(gpz, orc):
+    x = [np.random.default_rng(1).random(3000).astype(np.float32) for _ in range(4)]
+    s, _ = orc.compress(x, 1e-3, K=2, KF=2)
+    info = gpz.inspect(s[:32].tobytes())
+    assert info == dict(n=3000, nfields=4, block_size=1024, seg_bits=2, key_fields=2, nblocks=3)
+    bad = bytearray(s[:32].tobytes())
+    bad[0] ^= 1
+    with pytest.raises(gpz.GpzError):
+        gpz.inspect(bytes(bad))
+
+
+def test_invalid_arguments_rejected_before_device_work(gpz):
+    L = gpz.lib()
+    eb = np.array([1e-3], np.float32)
+    out = ctypes.c_uint64(0)
+    fake = (ctypes.c_void_p * 1)(ctypes.c_void_p(16))
+    p = gpz.params(1)
+    bad = gpz.params(1, block_size=100)
+    def args(prm, e, F=1):
+        return (ctypes.cast(fake, ctypes.c_void_p), 10, F, e.ctypes.data_as(ctypes.c_void_p),
+                ctypes.byref(prm), ctypes.c_void_p(16), 1000, ctypes.byref(out), None,
+                ctypes.c_void_p(16), 1 << 20, None)
+
+    assert L.gpz_compress(*args(bad, eb)) == gpz.GPZ_EINVAL
+    for e in (0.0, -1.0, np.inf, np.nan, 1e-38):
+        assert L.gpz_compress(*args(p, np.array([e], np.float32))) == gpz.GPZ_EINVAL
+    assert L.gpz_compress(*args(p, eb, F=0)) == gpz.GPZ_EINVAL
+    assert L.gpz_compress(*args(p, eb, F=65)) == gpz.GPZ_EINVAL
+    p512 = gpz.params(1, block_size=64)
+    assert L.gpz_compress(*args(p512, eb)) == gpz.GPZ_EUNSUPPORTED
+    assert L.gpz_decompress(None, 100, None, 10, 1, None, 0, None) == gpz.GPZ_EINVAL
+
+
+def test_strerror(gpz):
+    for c in range(-6, 1):
+        assert gpz.lib().gpz_strerror(c)
