@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Compress + decompress throughput of the GPZ hot path on one MI355X.
+
+Workload: a cosmology-like snapshot, 64,000,000 particles x 6 float32 SoA
+fields (x, y, z, vx, vy, vz), error bound 1e-3 of each field's value range.
+A step is one full compression (encode, length scan, record copy) followed by
+one full decompression (decode) of the snapshot, inputs resident in HBM.
+
+Prints one JSON line.  ``value`` = 2 * S / step time (original bytes moved
+through both directions per second).  ``roofline`` is for the kernel with the
+largest share of the step, timed with HIP events on its launch stream during
+the timed steps.  ``cpu_baseline`` is the CPU oracle on a bounded sample of
+the same snapshot, on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64_000_000)
+    ap.add_argument("--rel", type=float, default=1e-3)
+    ap.add_argument("--cpu-sample-blocks", type=int, default=1500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the compressor is single-GPU (blocks are independent; "
+              "see the sharding notes in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2508_10305_amd as gpz
+    from paper_2508_10305_amd import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    host = synth.cosmology(args.n, seed=1)
+    log(f"[bench] generated {args.n} x 6 in {time.time() - t0:.1f}s")
+    F = len(host)
+    n = args.n
+    S = 4 * n * F
+    fields = [torch.from_numpy(f).to(dev) for f in host]
+    torch.cuda.synchronize()
+
+    # value-range-relative bound -> absolute bounds (field range kernel)
+    t0 = time.perf_counter()
+    eb = gpz.rel_ebs(fields, args.rel)
+    range_ms = 1e3 * (time.perf_counter() - t0)
+
+    p = gpz.params(F)
+    comp = gpz.Compressor(n, F, p, device=dev)
+    outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(F)]
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    # correctness gate (untimed): full round trip, bound check
+    stream, perm = comp.compress(fields, eb, want_perm=True)
+    C = int(stream.numel())
+    gpz.decompress(stream, n, F, out=outs)
+    viol, maxerr = gpz.bound_check(fields, outs, eb, perm=perm)
+    assert int(viol.sum()) == 0, f"bound violated: {viol}"
+    log(f"[bench] S={S} C={C} CR={S / C:.3f} max_err/eb={(maxerr / eb).max():.4f}")
+    nb = (n + p.block_size - 1) // p.block_size
+    prefix_bytes = 4 * (8 + 2 * ((nb + 63) // 64) + F + nb)
+    rec_bytes = C - prefix_bytes
+
+    def step():
+        comp.compress_async(fields, eb)
+        gpz.decompress_async(comp.out, n, F, outs, err, p)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # plain-form per-call latency (host-synchronous compress + decompress)
+    lat = []
+    for _ in range(max(5, min(args.steps, 20))):
+        t0 = time.perf_counter()
+        comp.compress(fields, eb)
+        gpz.decompress(comp.out[:C], n, F, out=outs)
+        lat.append(1e3 * (time.perf_counter() - t0))
+    torch.cuda.synchronize()
+
+    # timed region
+    gpz.set_timing(True)
+    gpz.timing_collect()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    gpz.set_timing(False)
+    kt = gpz.timing_collect()
+    assert int(err.item()) == 0, "decoder flagged the stream"
+    ms_step = e0.elapsed_time(e1) / args.steps
+    avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
+    t_c = avg["encode"] + avg["scan"] + avg["copy"]
+    t_d = avg["decode"]
+    value = 2 * S / (ms_step * 1e-3) / 1e9
+
+    algo = {"encode": S + rec_bytes, "decode": C + S, "copy": 2 * rec_bytes, "scan": 12 * nb}
+    dominant = max(avg, key=lambda k: avg[k])
+    ach = algo[dominant] / (avg[dominant] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": dominant}
+    kernels = {k: {"ms": round(avg[k], 4),
+                   "algorithmic_GBps": round(algo[k] / (avg[k] * 1e-3) / 1e9, 1) if avg[k] else None}
+               for k in avg}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        m = min(n, args.cpu_sample_blocks * p.block_size)
+        sample = [np.ascontiguousarray(f[:m]) for f in host]
+        t0 = time.perf_counter()
+        s_ref, _ = oracle.compress(sample, eb)
+        t1 = time.perf_counter()
+        oracle.decompress(s_ref, m, F)
+        t2 = time.perf_counter()
+        cpu = {"value": round(2 * 4 * m * F / (t2 - t0) / 1e9, 5), "unit": "GB/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"first {m} particles ({m // p.block_size} blocks) x {F} fields of the "
+                         f"snapshot; compress {t1 - t0:.2f}s + decompress {t2 - t1:.2f}s, "
+                         f"single-threaded C"}
+
+    lat.sort()
+    rec = {
+        "metric": "compress+decompress GB/s and % HBM roofline at rel eb 1e-3; ratio; p99 latency",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cosmology-like snapshot, 64,000,000 particles x 6 float32 fields, "
+                               "rel eb 1e-3 of each field's range, one plain per-snapshot launch",
+                   "n": n, "fields": F, "block_size": p.block_size, "seg_bits": p.seg_bits,
+                   "rel_eb": args.rel},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "compress_GBps": round(S / (t_c * 1e-3) / 1e9, 2),
+        "decompress_GBps": round(S / (t_d * 1e-3) / 1e9, 2),
+        "compression_ratio": round(S / C, 4),
+        "max_abs_err_over_eb": round(float((maxerr / eb).max()), 6),
+        "kernels": kernels,
+        "field_range_ms": round(range_ms, 3),
+        "plain_latency_ms": {"p50": round(lat[len(lat) // 2], 3),
+                             "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3)},
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -106,10 +106,12 @@ int gpz_compress_async(const float *const *h_fields, uint64_t n, uint32_t nfield
 int gpz_decompress(const void *d_in, uint64_t in_bytes, float *const *h_fields_out, uint64_t n,
                    uint32_t nfields, void *d_ws, uint64_t ws_bytes, void *stream);
 
-/* As gpz_decompress without host synchronization or header checks against a
- * host copy: h_header must hold the first 32 + 4*F... bytes of the stream
- * (at least gpz_header_bytes(n, F, B)); a corrupt record sets
- * *d_error (device uint32, nonzero) instead of returning GPZ_ECORRUPT. */
+/* As gpz_decompress without any host synchronization (graph-capturable):
+ * the caller supplies the parameters the stream was written with (they are
+ * checked against its header on the device), in_bytes may be any upper
+ * bound of the stream size (e.g. the capacity of the compression output
+ * buffer), and a malformed stream sets the device flag *d_error (uint32,
+ * cleared by this call) instead of returning GPZ_ECORRUPT. */
 int gpz_decompress_async(const void *d_in, uint64_t in_bytes, float *const *h_fields_out,
                          uint64_t n, uint32_t nfields, const gpz_params *p, uint32_t *d_error,
                          void *stream);
@@ -145,13 +147,14 @@ typedef struct {
 } gpz_info;
 int gpz_inspect(const void *h_prefix, uint64_t bytes, gpz_info *out);
 
-/* Optional per-kernel timing with HIP events on the launch stream.  While
- * enabled, each gpz_compress / gpz_decompress call records events around
- * its kernels; gpz_last_timing returns the durations (ms) of the most recent
- * call on this thread: [0] encode, [1] scan, [2] compact copy (compress) or
- * [0] decode (decompress); count in *n. */
+/* Optional kernel timing with HIP events recorded on the launch stream.
+ * While enabled (per host thread), every compress / decompress call records
+ * an event pair around each of its kernels.  gpz_timing_collect waits for
+ * the recorded events, adds up the durations per kernel kind into
+ * total_ms[kind] with launch counts[kind] (kind 0 encode, 1 length scan,
+ * 2 record copy, 3 decode; arrays of nkinds entries) and clears the log. */
 int gpz_set_timing(int enable);
-int gpz_last_timing(float *ms, int max, int *n);
+int gpz_timing_collect(double *total_ms, uint32_t *counts, int nkinds);
 
 const char *gpz_strerror(int status);
 

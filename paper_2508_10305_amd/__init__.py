@@ -24,7 +24,7 @@ EXPORTS = (
     "gpz_default_params", "gpz_max_compressed_bytes", "gpz_compress_workspace_bytes",
     "gpz_decompress_workspace_bytes", "gpz_compress", "gpz_compress_async", "gpz_decompress",
     "gpz_decompress_async", "gpz_bound_check", "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
-    "gpz_set_timing", "gpz_last_timing", "gpz_strerror",
+    "gpz_set_timing", "gpz_timing_collect", "gpz_strerror",
 )
 
 
@@ -89,9 +89,9 @@ def _lib():
         L.gpz_inspect.restype = ctypes.c_int
         L.gpz_set_timing.argtypes = [ctypes.c_int]
         L.gpz_set_timing.restype = ctypes.c_int
-        L.gpz_last_timing.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int,
-                                      ctypes.POINTER(ctypes.c_int)]
-        L.gpz_last_timing.restype = ctypes.c_int
+        L.gpz_timing_collect.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_uint32), ctypes.c_int]
+        L.gpz_timing_collect.restype = ctypes.c_int
         L.gpz_strerror.argtypes = [ctypes.c_int]
         L.gpz_strerror.restype = ctypes.c_char_p
         _LIB = L
@@ -292,8 +292,12 @@ def set_timing(enable: bool):
     _lib().gpz_set_timing(1 if enable else 0)
 
 
-def last_timing() -> List[float]:
-    ms = (ctypes.c_float * 4)()
-    n = ctypes.c_int(0)
-    _lib().gpz_last_timing(ms, 4, ctypes.byref(n))
-    return [float(ms[i]) for i in range(n.value)]
+KERNEL_KINDS = ("encode", "scan", "copy", "decode")
+
+
+def timing_collect() -> dict:
+    """Per-kernel (total ms, launches) recorded since the last collection."""
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_uint32 * 4)()
+    _check(_lib().gpz_timing_collect(ms, cnt, 4), "gpz_timing_collect")
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}

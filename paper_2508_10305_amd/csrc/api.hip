@@ -12,35 +12,36 @@ using namespace gpz;
 
 namespace {
 
+// Optional kernel timing: HIP events recorded around each kernel on the
+// launch stream, collected later by gpz_timing_collect.
+enum { kEncode = 0, kScan = 1, kCopy = 2, kDecode = 3, kKinds = 4 };
+struct TimedLaunch {
+    int kind;
+    hipEvent_t a, b;
+};
 thread_local bool g_timing = false;
-thread_local float g_times[4];
-thread_local int g_ntimes = 0;
+thread_local std::vector<TimedLaunch> g_log;
 
 struct Timer {
-    hipEvent_t ev[5];
-    int n = 0;
-    bool on;
     hipStream_t s;
-    explicit Timer(hipStream_t st) : on(g_timing), s(st) {
-        if (on)
-            for (int i = 0; i < 5; i++)
-                if (hipEventCreate(&ev[i]) != hipSuccess) on = false;
-    }
-    void mark() {
-        if (on && n < 5) (void)hipEventRecord(ev[n++], s);
-    }
-    void finish() {  // call after the stream has been synchronized
+    bool on;
+    TimedLaunch cur{};
+    explicit Timer(hipStream_t st) : s(st), on(g_timing) {}
+    void begin(int kind) {
         if (!on) return;
-        g_ntimes = 0;
-        for (int i = 0; i + 1 < n; i++) {
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
-            g_times[g_ntimes++] = ms;
+        cur.kind = kind;
+        if (hipEventCreate(&cur.a) != hipSuccess) return;
+        if (hipEventCreate(&cur.b) != hipSuccess) {
+            (void)hipEventDestroy(cur.a);
+            return;
         }
+        (void)hipEventRecord(cur.a, s);
     }
-    ~Timer() {
-        if (on)
-            for (int i = 0; i < 5; i++) (void)hipEventDestroy(ev[i]);
+    void end() {
+        if (!on || !cur.a) return;
+        (void)hipEventRecord(cur.b, s);
+        g_log.push_back(cur);
+        cur = TimedLaunch{};
     }
 };
 
@@ -105,7 +106,8 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     if (!kernel_block_size(p.block_size)) return GPZ_EUNSUPPORTED;
     if (n > 0 && !h_fields) return GPZ_EINVAL;
     if (!d_out) return GPZ_EINVAL;
-    if (n > ((uint64_t)1 << 32) * p.block_size) return GPZ_EINVAL;  // block count fits 32 bits
+    // one 64-lane workgroup per block: the dispatch size (64 * blocks) must fit 32 bits
+    if (nblocks_of(n, p.block_size) > ((uint64_t)1 << 26)) return GPZ_EINVAL;
     for (uint32_t f = 0; f < F; f++) {
         if (!eb_valid(h_eb[f])) return GPZ_EINVAL;
         if (n > 0 && !h_fields[f]) return GPZ_EINVAL;
@@ -171,18 +173,19 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
 
     Timer tm(s);
     int rc = GPZ_OK;
-    tm.mark();
+    tm.begin(kEncode);
     if (rc == GPZ_OK) rc = to_status(launch_encode(ea, s));
-    tm.mark();
+    tm.end();
+    tm.begin(kScan);
     if (rc == GPZ_OK) rc = to_status(launch_scan(sa, s));
-    tm.mark();
+    tm.end();
+    tm.begin(kCopy);
     if (rc == GPZ_OK) rc = to_status(launch_copy(ca, s));
-    tm.mark();
+    tm.end();
     if (sync) {
         uint64_t total = 0;
         if (rc == GPZ_OK) rc = to_status(hipMemcpyAsync(&total, w.total, 8, hipMemcpyDeviceToHost, s));
         if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
-        tm.finish();
         if (h_out_bytes) *h_out_bytes = total;
         if (rc == GPZ_OK && total > cap) rc = GPZ_ENOSPC;
     }
@@ -237,14 +240,15 @@ int gpz_compress_async(const float* const* h_fields, uint64_t n, uint32_t nfield
 
 static int decompress_impl(const void* d_in, uint64_t in_bytes, float* const* h_out, uint64_t n,
                            uint32_t F, const gpz_params& p, uint32_t* d_err, hipStream_t s,
-                           Timer* tm) {
+                           bool exact) {
     const uint32_t B = p.block_size;
     const uint64_t nb = nblocks_of(n, B);
     const uint64_t pre = prefix_words(n, F, B);
-    if (in_bytes % 4 != 0 || in_bytes < 4 * pre) return GPZ_ECORRUPT;
+    if (nb > ((uint64_t)1 << 26)) return GPZ_EINVAL;
+    if (in_bytes < 4 * pre || (exact && in_bytes % 4 != 0)) return GPZ_ECORRUPT;
     if (nb == 0) {
         // nothing to decode; the stream is the header and the eb table
-        if (in_bytes != 4 * pre) return GPZ_ECORRUPT;
+        if (exact && in_bytes != 4 * pre) return GPZ_ECORRUPT;
         std::vector<uint32_t> h(pre);
         if (hipMemcpyAsync(h.data(), d_in, 4 * pre, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
@@ -267,10 +271,12 @@ static int decompress_impl(const void* d_in, uint64_t in_bytes, float* const* h_
     da.nblocks = (uint32_t)nb;
     da.prefix = pre;
     da.err = d_err;
+    da.exact = exact ? 1u : 0u;
     int rc = to_status(launch_fill_u32(d_err, 0u, 1, s));
-    if (tm) tm->mark();
+    Timer tm(s);
+    tm.begin(kDecode);
     if (rc == GPZ_OK) rc = to_status(launch_decode(da, s));
-    if (tm) tm->mark();
+    tm.end();
     return rc;
 }
 
@@ -300,12 +306,10 @@ int gpz_decompress(const void* d_in, uint64_t in_bytes, float* const* h_fields_o
     } else if (ws_bytes < gpz_decompress_workspace_bytes()) {
         return GPZ_EINVAL;
     }
-    Timer tm(s);
-    rc = decompress_impl(d_in, in_bytes, h_fields_out, n, nfields, p, err, s, &tm);
+    rc = decompress_impl(d_in, in_bytes, h_fields_out, n, nfields, p, err, s, true);
     uint32_t e = 0;
     if (rc == GPZ_OK) rc = to_status(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s));
     if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
-    tm.finish();
     if (owned) (void)hipFree(err);
     if (rc == GPZ_OK && e) rc = GPZ_ECORRUPT;
     return rc;
@@ -320,7 +324,7 @@ int gpz_decompress_async(const void* d_in, uint64_t in_bytes, float* const* h_fi
     if (!params_ok(nfields, p)) return GPZ_EINVAL;
     if (!kernel_block_size(p.block_size)) return GPZ_EUNSUPPORTED;
     return decompress_impl(d_in, in_bytes, h_fields_out, n, nfields, p, d_error,
-                           static_cast<hipStream_t>(stream), nullptr);
+                           static_cast<hipStream_t>(stream), false);
 }
 
 int gpz_bound_check(const float* const* h_orig, const float* const* h_recon,
@@ -421,12 +425,27 @@ int gpz_set_timing(int enable) {
     return GPZ_OK;
 }
 
-int gpz_last_timing(float* ms, int max, int* n) {
-    if (!ms || !n) return GPZ_EINVAL;
-    int k = g_ntimes < max ? g_ntimes : max;
-    for (int i = 0; i < k; i++) ms[i] = g_times[i];
-    *n = k;
-    return GPZ_OK;
+int gpz_timing_collect(double* total_ms, uint32_t* counts, int nkinds) {
+    if (!total_ms || !counts || nkinds < 1) return GPZ_EINVAL;
+    for (int k = 0; k < nkinds; k++) {
+        total_ms[k] = 0.0;
+        counts[k] = 0;
+    }
+    int rc = GPZ_OK;
+    for (auto& t : g_log) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(t.b) != hipSuccess ||
+            hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
+            rc = GPZ_EDEVICE;
+        if (t.kind < nkinds) {
+            total_ms[t.kind] += ms;
+            counts[t.kind]++;
+        }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    g_log.clear();
+    return rc;
 }
 
 const char* gpz_strerror(int status) {

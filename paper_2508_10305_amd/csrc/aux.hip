@@ -111,7 +111,12 @@ __global__ __launch_bounds__(256) void bound_check_kernel(BoundArgs a) {
     double m = 0.0;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n;
          j += (uint64_t)gridDim.x * blockDim.x) {
-        float xo = x[a.perm ? a.perm[j] : j];
+        uint64_t src = a.perm ? a.perm[j] : j;
+        if (src >= a.n) {  // not a permutation of [0, n): count, do not read
+            v++;
+            continue;
+        }
+        float xo = x[src];
         float yr = y[j];
         double d = __builtin_fabs((double)yr - (double)xo);
         if (!__builtin_isnan(d) && d > m) m = d;

@@ -74,9 +74,19 @@ __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
     const uint32_t len = lens[b];
     bool bad = off + len > rec_total;
     if (b == 0 && (sup[0] | sup[1]) != 0u) bad = true;
-    if (b + 1 == a.nblocks && off + len != rec_total) bad = true;
+    if (a.exact && b + 1 == a.nblocks && off + len != rec_total) bad = true;
     for (uint32_t f = lane; f < F; f += 64)
         if (!eb_ok(u2f(ebt[f]))) bad = true;
+    if (lane < kHeaderWords) {
+        // the header must describe the stream the caller asked for
+        const uint32_t expect[kHeaderWords] = {kMagic, kVersion, (uint32_t)(a.n & 0xFFFFFFFFu),
+                                               (uint32_t)(a.n >> 32), F, a.B, K | (KF << 8),
+                                               a.nblocks};
+        uint32_t want = expect[0];
+#pragma unroll
+        for (uint32_t k = 1; k < kHeaderWords; k++) want = lane == k ? expect[k] : want;
+        if (a.in[lane] != want) bad = true;
+    }
     bad = __any(bad);
     if (b == first && sb > 0) {
         // consistency of this superblock's offset with the previous one

@@ -76,6 +76,7 @@ struct DecodeArgs {
     uint32_t nblocks;
     uint64_t prefix;       // words before the record area
     uint32_t* err;         // set nonzero on a malformed record
+    uint32_t exact;        // in_words is the exact stream length (else an upper bound)
 };
 
 // ------------------------------------------------------------ wave64 primitives
