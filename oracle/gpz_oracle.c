@@ -121,8 +121,10 @@ float oracle_block_min(const float *x, uint32_t n) {
  * result is rounded to the nearest integer, ties to even.  The value is an
  * outlier, to be stored verbatim, when the index falls outside [0, 2^24-1]
  * (32-bit intermediates, Sec. 5.3) or when the float32 reconstruction
- * fma(q, 2 eb, min) (Sec. 5.1, explicit FMA) misses the bound; the bound
- * test is |xr - x| <= eb in IEEE double. */
+ * xr = fma(q, 2 eb, min) (Sec. 5.1, explicit FMA) does not pass the bound
+ * test fabsf(xr - x) < eb, evaluated in float32.  Rounding is monotone and
+ * eb is a float, so a pass implies that the exact error is below eb: the
+ * bound is respected strictly (Sec. 3.2). */
 uint32_t oracle_quantize(float x, float lo, float eb, int *outlier) {
     float twoeb = 2.0f * eb;
     float inv = 1.0f / twoeb;
@@ -132,7 +134,8 @@ uint32_t oracle_quantize(float x, float lo, float eb, int *outlier) {
     uint32_t q = 0;
     if (in_range) q = (uint32_t)rintf(t);
     float xr = fmaf((float)q, twoeb, lo);
-    int ok = in_range && (fabs((double)xr - (double)x) <= (double)eb);
+    float err = xr - x;
+    int ok = in_range && (fabsf(err) < eb);
     *outlier = !ok;
     return q;
 }
