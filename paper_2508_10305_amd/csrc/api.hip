@@ -70,7 +70,8 @@ uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 struct CompressWs {
     uint32_t* temp;
     uint32_t* lens;
-    uint64_t* offs;
+    uint32_t* supsum;
+    uint64_t* supoff;
     uint64_t* total;
     uint32_t slot_words;
     uint64_t bytes;
@@ -85,8 +86,11 @@ CompressWs layout(uint64_t n, uint32_t F, uint32_t B, char* base) {
     o = align256(o + nb * w.slot_words * 4ull);
     w.lens = reinterpret_cast<uint32_t*>(base + o);
     o = align256(o + nb * 4ull);
-    w.offs = reinterpret_cast<uint64_t*>(base + o);
-    o = align256(o + nb * 8ull);
+    const uint64_t ns = nsuper_of(nb);
+    w.supsum = reinterpret_cast<uint32_t*>(base + o);
+    o = align256(o + ns * 4ull);
+    w.supoff = reinterpret_cast<uint64_t*>(base + o);
+    o = align256(o + ns * 8ull);
     w.total = reinterpret_cast<uint64_t*>(base + o);
     o = align256(o + 64);
     w.bytes = o;
@@ -147,19 +151,20 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     ea.slot_words = w.slot_words;
     ea.temp = w.temp;
     ea.lens = w.lens;
+    ea.supsum = w.supsum;
     ea.perm = d_perm;
 
     ScanArgs sa{};
-    sa.lens = w.lens;
-    sa.offs = w.offs;
+    sa.supsum = w.supsum;
+    sa.supoff = w.supoff;
     sa.total_bytes = w.total;
     sa.ext_bytes = d_out_bytes;
-    sa.nblocks = (uint32_t)nb;
+    sa.nsuper = (uint32_t)nsuper_of(nb);
     sa.prefix = prefix_words(n, F, B);
 
     ca.temp = w.temp;
     ca.lens = w.lens;
-    ca.offs = w.offs;
+    ca.supoff = w.supoff;
     ca.total_bytes = w.total;
     ca.out = static_cast<uint32_t*>(d_out);
     ca.capacity = cap;
@@ -172,7 +177,7 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     ca.KF = p.key_fields;
 
     Timer tm(s);
-    int rc = GPZ_OK;
+    int rc = to_status(launch_fill_u32(w.supsum, 0u, nsuper_of(nb), s));
     tm.begin(kEncode);
     if (rc == GPZ_OK) rc = to_status(launch_encode(ea, s));
     tm.end();

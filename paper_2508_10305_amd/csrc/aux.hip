@@ -10,18 +10,18 @@ namespace {
 
 constexpr uint32_t kScanThreads = 1024;
 
-// Single-workgroup exclusive scan: thread t sums a contiguous chunk, the
-// chunk totals are scanned in LDS, then each thread writes its chunk's
-// offsets.
+// Exclusive scan of the per-superblock record sizes (one workgroup; there
+// are only ceil(nblocks / 64) of them): thread t sums a contiguous chunk, the
+// chunk totals are scanned in LDS, then each thread writes its offsets.
 __global__ __launch_bounds__(kScanThreads) void scan_lengths(ScanArgs a) {
     __shared__ uint64_t part[kScanThreads];
     const uint32_t t = threadIdx.x;
-    const uint32_t nb = a.nblocks;
-    const uint32_t chunk = (nb + kScanThreads - 1) / kScanThreads;
+    const uint32_t ns = a.nsuper;
+    const uint32_t chunk = (ns + kScanThreads - 1) / kScanThreads;
     const uint32_t lo = t * chunk;
-    const uint32_t hi = lo + chunk < nb ? lo + chunk : nb;
+    const uint32_t hi = lo + chunk < ns ? lo + chunk : ns;
     uint64_t sum = 0;
-    for (uint32_t i = lo; i < hi; i++) sum += a.lens[i];
+    for (uint32_t i = lo; i < hi; i++) sum += a.supsum[i];
     part[t] = sum;
     __syncthreads();
     for (uint32_t o = 1; o < kScanThreads; o <<= 1) {
@@ -32,8 +32,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_lengths(ScanArgs a) {
     }
     uint64_t run = part[t] - sum;
     for (uint32_t i = lo; i < hi; i++) {
-        a.offs[i] = run;
-        run += a.lens[i];
+        a.supoff[i] = run;
+        run += a.supsum[i];
     }
     if (t == kScanThreads - 1) {
         uint64_t bytes = 4 * (a.prefix + part[t]);
@@ -70,8 +70,11 @@ __global__ __launch_bounds__(256) void copy_records(CopyArgs a) {
         for (uint32_t f = lane; f < a.F; f += 64) ebt[f] = a.eb_bits[f];
     }
     if (b >= a.nblocks) return;
+    // offset = superblock offset + lengths of the earlier blocks of the superblock
+    const uint32_t sb = b / kSuper, first = sb * kSuper;
+    const uint32_t before = wave_sum_u32(first + lane < b ? a.lens[first + lane] : 0u);
     const uint32_t len = a.lens[b];
-    const uint64_t off = a.offs[b];
+    const uint64_t off = a.supoff[sb] + before;
     if (lane == 0) {
         lt[b] = len;
         if (b % kSuper == 0) {

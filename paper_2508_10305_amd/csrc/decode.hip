@@ -3,8 +3,13 @@
 // superblock table, undoes the delta and run-length coding of the segment
 // IDs, unpacks the fixed-length payloads, rebuilds every value with
 // fma(q, 2eb, lo), patches outliers and stores the block in sorted order.
-// Every read of the record is checked against its length first; a malformed
-// record sets the error flag and the block is skipped.
+//
+// Each coded array is first copied into LDS with coalesced loads; values are
+// then extracted from LDS.  Outputs are written "striped": lane l produces
+// positions 256k + 4l + {0..3}, so one 16-byte store per lane covers 1 KB of
+// contiguous output per instruction.  Every read of the record is checked
+// against its length first; a malformed record sets the error flag and the
+// block is skipped.
 #include "gpz_internal.h"
 
 namespace gpz {
@@ -15,44 +20,48 @@ __device__ __forceinline__ uint32_t pad_addr(uint32_t p) {
     return p + 4 * (p / ITEMS);
 }
 
-// Value i of a fixed-length array of width w (bits [i*w, i*w+w)).
-__device__ __forceinline__ uint32_t unpack_one(const uint32_t* __restrict__ arr, uint32_t i,
-                                               uint32_t w) {
-    if (w == 0) return 0u;
-    uint32_t bit = i * w;
-    uint32_t wd = bit >> 5, sh = bit & 31u;
-    uint32_t v = arr[wd] >> sh;
-    if (sh + w > 32u) v |= arr[wd + 1] << (32u - sh);
-    return w == 32u ? v : (v & ((1u << w) - 1u));
-}
-
 __device__ __forceinline__ bool eb_ok(float eb) {
     return __builtin_isfinite(eb) && eb >= 0x1p-120f && eb <= 0x1p120f;
 }
 
-template <int ITEMS>
-__device__ __forceinline__ void store_block(float* __restrict__ y, uint64_t base, uint32_t nb,
-                                            uint32_t lane, const uint32_t* stage) {
-    float* p = y + base + (uint64_t)lane * ITEMS;
-    const uint32_t* src = stage + lane * (ITEMS + 4);
-    const bool full = (lane + 1) * ITEMS <= nb;
-    if (full && ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)) {
-        const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
-        u32x4* p4 = reinterpret_cast<u32x4*>(p);
-#pragma unroll
-        for (int k = 0; k < ITEMS / 4; k++) __builtin_nontemporal_store(s4[k], p4 + k);
-    } else {
-#pragma unroll
-        for (int j = 0; j < ITEMS; j++)
-            if (lane * ITEMS + j < nb) p[j] = u2f(src[j]);
+// Copy `count` words from global memory into LDS (coalesced, 4 in flight).
+__device__ __forceinline__ void stage_words(uint32_t* __restrict__ dst,
+                                            const uint32_t* __restrict__ src, uint32_t count,
+                                            uint32_t lane) {
+    uint32_t k = lane;
+    for (; k + 192 < count; k += 256) {
+        uint32_t a = src[k], b = src[k + 64], c = src[k + 128], d = src[k + 192];
+        dst[k] = a;
+        dst[k + 64] = b;
+        dst[k + 128] = c;
+        dst[k + 192] = d;
     }
+    for (; k < count; k += 64) dst[k] = src[k];
 }
+
+// Value i of a fixed-length array of width w held in LDS (bits [i*w, i*w+w)).
+__device__ __forceinline__ uint32_t extract(const uint32_t* __restrict__ words, uint32_t i,
+                                            uint32_t w, uint32_t mask) {
+    uint32_t bit = i * w;
+    uint32_t wd = bit >> 5;
+    uint32_t lo = words[wd], hi = words[wd + 1];
+    return __builtin_amdgcn_alignbit(hi, lo, bit & 31u) & mask;
+}
+
+__device__ __forceinline__ uint32_t low_mask(uint32_t w) { return w >= 32u ? ~0u : ((1u << w) - 1u); }
 
 template <int ITEMS>
 __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
     constexpr uint32_t B = 64 * ITEMS;
-    constexpr uint32_t kStageWords = 64 * (ITEMS + 4);
-    __shared__ __align__(16) uint32_t stage[kStageWords];
+    constexpr uint32_t G = ITEMS / 4;  // 16-byte groups per lane
+    // widest coded arrays: payload 24 bits/value; gaps 15 + counts 12 bits
+    constexpr uint32_t kPay = (B * 24) / 32 + 2;
+    constexpr uint32_t kRle = (B * 15) / 32 + (B * 12) / 32 + 4;
+    constexpr uint32_t kWords = kPay > kRle ? kPay : kRle;
+    constexpr uint32_t kPadB = 64 * (ITEMS + 4);
+    __shared__ __align__(16) uint32_t words[kWords];
+    __shared__ __align__(16) uint32_t keys[kPadB];
+    __shared__ __align__(16) uint32_t ystage[B];
 
     const uint32_t lane = threadIdx.x;
     const uint32_t b = blockIdx.x;
@@ -87,14 +96,13 @@ __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
         for (uint32_t k = 1; k < kHeaderWords; k++) want = lane == k ? expect[k] : want;
         if (a.in[lane] != want) bad = true;
     }
-    bad = __any(bad);
     if (b == first && sb > 0) {
         // consistency of this superblock's offset with the previous one
         uint32_t pl = lens[first - kSuper + lane];
         uint64_t prev = ((uint64_t)sup[2 * sb - 2] | ((uint64_t)sup[2 * sb - 1] << 32));
         if (prev + wave_sum_u32(pl) != off) bad = true;
     }
-    if (bad) {
+    if (__any(bad)) {
         if (lane == 0) *a.err = 1u;
         return;
     }
@@ -135,15 +143,20 @@ __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
     }
 
     // ---- undo delta + run-length coding (Sec. 4.3)
+    stage_words(words, rec + 2, gw + cw, lane);
+    __syncthreads();
     uint32_t g1[ITEMS], c1[ITEMS];
     uint32_t gs = 0, cs = 0;
+    {
+        const uint32_t gm = low_mask(w_gap), cm = low_mask(w_cnt);
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        uint32_t i = lane * ITEMS + j;
-        g1[j] = i < U ? unpack_one(rec + 2, i, w_gap) + 1u : 0u;
-        c1[j] = i < U ? unpack_one(rec + 2 + gw, i, w_cnt) + 1u : 0u;
-        gs += g1[j];
-        cs += c1[j];
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t i = lane * ITEMS + j;
+            g1[j] = i < U ? extract(words, i, w_gap, gm) + 1u : 0u;
+            c1[j] = i < U ? extract(words + gw, i, w_cnt, cm) + 1u : 0u;
+            gs += g1[j];
+            cs += c1[j];
+        }
     }
     const uint32_t gincl = wave_incl_scan_u32(gs), cincl = wave_incl_scan_u32(cs);
     const uint32_t gtot = (uint32_t)__shfl((int)gincl, 63), ctot = (uint32_t)__shfl((int)cincl, 63);
@@ -152,9 +165,9 @@ __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
         if (lane == 0) *a.err = 1u;
         return;
     }
-    // mark run starts: stage[start] = ID (IDs increase, so a prefix maximum
-    // over positions recovers the ID of every position)
-    for (uint32_t p = lane; p < nb; p += 64) stage[pad_addr<ITEMS>(p)] = 0u;
+    // mark run starts with their ID; IDs increase with position, so a prefix
+    // maximum over positions gives every position its ID
+    for (uint32_t p = lane; p < B; p += 64) keys[pad_addr<ITEMS>(p)] = 0u;
     __syncthreads();
     {
         uint32_t u = gincl - gs, st = cincl - cs;
@@ -163,32 +176,49 @@ __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
             uint32_t i = lane * ITEMS + j;
             if (i < U) {
                 u += g1[j];
-                stage[pad_addr<ITEMS>(st)] = u - 1u;
+                keys[pad_addr<ITEMS>(st)] = u - 1u;
                 st += c1[j];
             }
         }
     }
     __syncthreads();
-    uint32_t key[ITEMS];
     {
+        uint32_t key[ITEMS];
         uint32_t run = 0;
+        const uint4* kb = reinterpret_cast<const uint4*>(keys + lane * (ITEMS + 4));
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            uint32_t p = lane * ITEMS + j;
-            uint32_t v = p < nb ? stage[pad_addr<ITEMS>(p)] : 0u;
-            run = max(run, v);
-            key[j] = run;
+        for (int g = 0; g < G; g++) {
+            uint4 t = kb[g];
+            run = max(run, t.x);
+            key[4 * g + 0] = run;
+            run = max(run, t.y);
+            key[4 * g + 1] = run;
+            run = max(run, t.z);
+            key[4 * g + 2] = run;
+            run = max(run, t.w);
+            key[4 * g + 3] = run;
         }
         uint32_t carry = wave_incl_max_u32(run);
         carry = (uint32_t)__shfl_up((int)carry, 1);
         if (lane == 0) carry = 0;
+        __syncthreads();
+        uint4* kw = reinterpret_cast<uint4*>(keys + lane * (ITEMS + 4));
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) key[j] = max(key[j], carry);
+        for (int g = 0; g < G; g++)
+            kw[g] = make_uint4(max(key[4 * g], carry), max(key[4 * g + 1], carry),
+                               max(key[4 * g + 2], carry), max(key[4 * g + 3], carry));
     }
     __syncthreads();
+    // striped positions of this lane: p = 256 g + 4 lane + e
+    uint32_t skey[ITEMS];
+#pragma unroll
+    for (int g = 0; g < G; g++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) skey[4 * g + e] = keys[pad_addr<ITEMS>(256 * g + 4 * lane + e)];
 
     // ---- fields
     uint64_t pos = 2 + gw + cw;
+    const bool full = nb == B;
     for (uint32_t f = 0; f < F; f++) {
         if (pos + 2 > len) {
             bad = true;
@@ -208,42 +238,68 @@ __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
             bad = true;
             break;
         }
-        const float eb = u2f(ebt[f]);
-        if (!eb_ok(eb)) {
-            bad = true;
-            break;
-        }
-        const float twoeb = 2.0f * eb;
-        const uint32_t* pay = rec + pos + 2;
+        const float twoeb = 2.0f * u2f(ebt[f]);
+        __syncthreads();  // previous users of `words` are done
+        stage_words(words, rec + pos + 2, pw, lane);
+        __syncthreads();
+        const uint32_t mask = low_mask(w);
         const uint32_t kmask = (1u << K) - 1u;
+        const bool keyf = f < KF;
+        uint32_t y[ITEMS];
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            uint32_t p = lane * ITEMS + j;
-            if (p < nb) {
-                uint32_t v = unpack_one(pay, p, w);
-                uint32_t q = f < KF ? ((((key[j] >> shift) & kmask) << s) | v) : v;
-                stage[pad_addr<ITEMS>(p)] = f2u(__builtin_fmaf((float)q, twoeb, lo));
+        for (int g = 0; g < G; g++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t p = 256 * g + 4 * lane + e;
+                uint32_t v = extract(words, p, w, mask);
+                uint32_t q = keyf ? ((((skey[4 * g + e] >> shift) & kmask) << s) | v) : v;
+                y[4 * g + e] = f2u(__builtin_fmaf((float)q, twoeb, lo));
+            }
+        if (nout) {
+            // patch outliers through LDS
+            const uint32_t* ol = rec + pos + 2 + pw;
+#pragma unroll
+            for (int g = 0; g < G; g++)
+                reinterpret_cast<uint4*>(ystage)[64 * g + lane] =
+                    make_uint4(y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]);
+            __syncthreads();
+            bool obad = false;
+            for (uint32_t k = lane; k < nout; k += 64) {
+                uint32_t op = ol[2 * k];
+                uint32_t prevp = k ? ol[2 * k - 2] : 0u;
+                if (op >= nb || (k && prevp >= op)) obad = true;
+                else ystage[op] = ol[2 * k + 1];
+            }
+            if (__any(obad)) {
+                bad = true;
+                break;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                uint4 t = reinterpret_cast<const uint4*>(ystage)[64 * g + lane];
+                y[4 * g] = t.x;
+                y[4 * g + 1] = t.y;
+                y[4 * g + 2] = t.z;
+                y[4 * g + 3] = t.w;
             }
         }
-        __syncthreads();
-        const uint32_t* ol = pay + pw;
-        bool obad = false;
-        for (uint32_t k = lane; k < nout; k += 64) {
-            uint32_t op = ol[2 * k];
-            uint32_t prevp = k ? ol[2 * k - 2] : 0u;
-            if (op >= nb || (k && prevp >= op)) {
-                obad = true;
-            } else {
-                stage[pad_addr<ITEMS>(op)] = ol[2 * k + 1];
+        float* yf = a.y[f] + base;
+        if (full && ((reinterpret_cast<uintptr_t>(a.y[f]) & 15u) == 0)) {
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                u32x4 t = {y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]};
+                __builtin_nontemporal_store(t, reinterpret_cast<u32x4*>(yf + 256 * g + 4 * lane));
             }
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; g++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t p = 256 * g + 4 * lane + e;
+                    if (p < nb) yf[p] = u2f(y[4 * g + e]);
+                }
         }
-        if (__any(obad)) {
-            bad = true;
-            break;
-        }
-        __syncthreads();
-        store_block<ITEMS>(a.y[f], base, nb, lane, stage);
-        __syncthreads();
         pos += 2 + pw + 2 * (uint64_t)nout;
     }
     if (bad || pos != len) {

@@ -7,7 +7,9 @@
 // [l*ITEMS, (l+1)*ITEMS) of its block ("blocked"), so per-lane sequential
 // order followed by lane order is input order; that is what makes the LDS
 // radix sort stable.  One wave per workgroup: __syncthreads() only orders LDS
-// traffic, it never waits for another wave.
+// traffic, it never waits for another wave.  Full blocks take a path
+// without per-item bounds checks; only the last block of a snapshot can be
+// partial.
 #include "gpz_internal.h"
 
 namespace gpz {
@@ -32,26 +34,26 @@ __device__ __forceinline__ uint32_t pad_addr(uint32_t p) {
     return p + 4 * (p / ITEMS);
 }
 
-// Exact copy of the quantizer rule: t = (x - lo) * inv (two IEEE float ops),
-// q = rint(t) when t lies in [0, 2^24-1] (else 0), outlier when out of range
-// or when fma(q, 2eb, lo) misses x by more than eb (tested in double).
+// Quantizer: t = (x - lo) * inv (two IEEE float ops), q = rint(t) when t lies
+// in [0, 2^24-1] (else 0); the value stays on the grid only when the float32
+// error of xr = fma(q, 2eb, lo) is below eb (which bounds the exact error
+// strictly), otherwise it is an outlier stored verbatim.
 __device__ __forceinline__ uint32_t quantize(float x, float lo, float inv, float twoeb, float eb,
                                              bool& outlier) {
     float t = (x - lo) * inv;
     bool in = (t >= 0.0f) && (t <= kQMax);
     uint32_t q = in ? (uint32_t)__builtin_rintf(t) : 0u;
     float xr = __builtin_fmaf((float)q, twoeb, lo);
-    bool ok = in && (__builtin_fabs((double)xr - (double)x) <= (double)eb);
+    bool ok = in && (__builtin_fabsf(xr - x) < eb);
     outlier = !ok;
     return q;
 }
 
-template <int ITEMS>
+template <int ITEMS, bool FULL>
 __device__ __forceinline__ void load_block(const float* __restrict__ x, uint64_t base, uint32_t nb,
                                            uint32_t lane, float (&v)[ITEMS]) {
     const float* p = x + base + (uint64_t)lane * ITEMS;
-    const bool full = (lane + 1) * ITEMS <= nb;
-    if (full && ((reinterpret_cast<uintptr_t>(p) & 15u) == 0)) {
+    if (FULL && ((reinterpret_cast<uintptr_t>(x) & 15u) == 0)) {
         const f32x4* p4 = reinterpret_cast<const f32x4*>(p);
 #pragma unroll
         for (int k = 0; k < ITEMS / 4; k++) {
@@ -65,66 +67,88 @@ __device__ __forceinline__ void load_block(const float* __restrict__ x, uint64_t
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             uint32_t i = lane * ITEMS + j;
-            v[j] = i < nb ? p[j] : 0.0f;
+            v[j] = (FULL || i < nb) ? p[j] : 0.0f;
         }
     }
 }
 
-// Block minimum over finite values; zero (either sign) and "none" give +0.
-template <int ITEMS>
-__device__ __forceinline__ float block_low(const float (&v)[ITEMS], uint32_t lane, uint32_t nb) {
+// Quantize one field of the block: q | outlier << 31 per value (0 beyond the
+// block); returns the block minimum lo (finite values only; zero and "none"
+// give +0).
+template <int ITEMS, bool FULL>
+__device__ __forceinline__ float quantize_field(const float (&v)[ITEMS], uint32_t nb,
+                                                uint32_t lane, float inv, float twoeb, float eb,
+                                                uint32_t (&q)[ITEMS]) {
     float m = __builtin_inff();
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        bool ok = (lane * ITEMS + j < nb) && __builtin_isfinite(v[j]);
+        bool ok = (FULL || lane * ITEMS + j < nb) && __builtin_isfinite(v[j]);
         m = fminf(m, ok ? v[j] : __builtin_inff());
     }
     m = wave_min_f32(m);
-    return (m == __builtin_inff() || m == 0.0f) ? 0.0f : m;
-}
-
-// Quantize one field of the block: q | outlier << 31 per value (0 for
-// positions beyond the block), returns lo.
-template <int ITEMS>
-__device__ __forceinline__ float quantize_field(const float* __restrict__ x, uint64_t base,
-                                                uint32_t nb, uint32_t lane, float inv, float twoeb,
-                                                float eb, uint32_t (&q)[ITEMS]) {
-    float v[ITEMS];
-    load_block<ITEMS>(x, base, nb, lane, v);
-    float lo = block_low<ITEMS>(v, lane, nb);
+    const float lo = (m == __builtin_inff() || m == 0.0f) ? 0.0f : m;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         bool o;
         uint32_t qq = quantize(v[j], lo, inv, twoeb, eb, o);
-        q[j] = (lane * ITEMS + j < nb) ? (qq | ((uint32_t)o << 31)) : 0u;
+        qq |= (uint32_t)o << 31;
+        q[j] = (FULL || lane * ITEMS + j < nb) ? qq : 0u;
     }
     return lo;
 }
 
-// Fixed-length packing (Sec. 4.3): value i of `count` values, width w, goes
-// to bits [i*w, i*w+w) of dst.  Bits are OR-ed into an LDS staging area
-// (order-independent), then copied out with coalesced stores.
+// Fixed-length packing (Sec. 4.3): value i of `count` values of width w
+// (1 <= w <= 24) goes to bits [i*w, i*w+w) of dst.  Lane l packs its ITEMS
+// consecutive values (blocked in v).  Bit positions inside the lane's
+// segment, j*w, are the same for every lane, so the lane accumulates into one
+// register and flushes on wave-uniform branches; each completed segment word
+// is shifted to the lane's start bit with one 64-bit shift and stored into
+// LDS staging.  The lane owning bit 0 of a word stores it; a lane whose
+// segment starts inside a word ORs its part in after a barrier.  The staged
+// words are then copied to dst with coalesced stores.
 template <int ITEMS>
-__device__ __forceinline__ void pack_store(const uint32_t (&val)[ITEMS], uint32_t count, uint32_t w,
+__device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t count, uint32_t w,
                                            uint32_t* __restrict__ dst, uint32_t* stage,
                                            uint32_t lane) {
     const uint32_t nwords = words_for(count, w);
     if (nwords == 0) return;
-    for (uint32_t k = lane; k < nwords; k += 64) stage[k] = 0u;
-    __syncthreads();
+    const bool active = lane * ITEMS < count;
+    const uint32_t S = lane * ITEMS * w;            // first bit of the lane's segment
+    const uint32_t w0 = S >> 5, shl = S & 31u;
+    const uint32_t lastw = (S + ITEMS * w - 1) >> 5;  // last word the segment touches
+    uint32_t acc = 0u, prev = 0u, first = 0u;
+    uint32_t k = 0, pos = 0;  // segment word index and bit position in it (uniform)
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        uint32_t i = lane * ITEMS + j;
-        uint32_t v = val[j];
-        if (i < count && v != 0u) {
-            uint32_t bit = i * w;
-            uint32_t wd = bit >> 5, sh = bit & 31u;
-            atomicOr(&stage[wd], v << sh);
-            if (sh + w > 32u) atomicOr(&stage[wd + 1], v >> (32u - sh));
+        acc |= v[j] << pos;
+        pos += w;
+        if (pos >= 32u) {
+            const uint32_t gi = w0 + k;
+            const uint32_t word = (uint32_t)((((uint64_t)acc << 32) | prev) >> (32u - shl));
+            if (active && gi < nwords && (k > 0 || shl == 0)) stage[gi] = word;
+            if (k == 0) first = acc;
+            prev = acc;
+            pos -= 32u;
+            acc = pos ? v[j] >> (w - pos) : 0u;
+            k++;
         }
     }
+    if (pos > 0u) {  // last, partly filled segment word
+        const uint32_t gi = w0 + k;
+        const uint32_t word = (uint32_t)((((uint64_t)acc << 32) | prev) >> (32u - shl));
+        if (active && gi < nwords && (k > 0 || shl == 0)) stage[gi] = word;
+        if (k == 0) first = acc;
+        prev = acc;
+        k++;
+    }
+    if (shl != 0u) {  // spill-over of the segment's top bits into one more word
+        const uint32_t gi = w0 + k;
+        if (active && gi <= lastw && gi < nwords) stage[gi] = prev >> (32u - shl);
+    }
     __syncthreads();
-    for (uint32_t k = lane; k < nwords; k += 64) dst[k] = stage[k];
+    if (active && shl != 0u && w0 < nwords) atomicOr(&stage[w0], first << shl);
+    __syncthreads();
+    for (uint32_t i = lane; i < nwords; i += 64) dst[i] = stage[i];
     __syncthreads();
 }
 
@@ -133,7 +157,7 @@ __device__ __forceinline__ void pack_store(const uint32_t (&val)[ITEMS], uint32_
 // its private counter column give the within-lane rank), a raking scan in
 // (digit, lane) order gives every (digit, lane) its first slot, and items are
 // scattered to their slots and read back blocked.
-template <int ITEMS>
+template <int ITEMS, bool FULL>
 __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, uint32_t nb,
                                            uint32_t lane, uint32_t* cnt, uint32_t* kvbuf) {
     uint4* c4 = reinterpret_cast<uint4*>(cnt);
@@ -144,7 +168,8 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         uint32_t d = (kv[j] >> (16 + sh)) & (kDigits - 1);
-        rank[j] = (lane * ITEMS + j < nb) ? atomicAdd(&cnt[counter_addr(d, lane)], 1u) : 0u;
+        if (FULL || lane * ITEMS + j < nb) rank[j] = atomicAdd(&cnt[counter_addr(d, lane)], 1u);
+        else rank[j] = 0u;
     }
     __syncthreads();
     {
@@ -175,7 +200,7 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        if (lane * ITEMS + j < nb) {
+        if (FULL || lane * ITEMS + j < nb) {
             uint32_t d = (kv[j] >> (16 + sh)) & (kDigits - 1);
             uint32_t dest = cnt[counter_addr(d, lane)] + rank[j];
             kvbuf[pad_addr<ITEMS>(dest)] = kv[j];
@@ -194,19 +219,12 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
     __syncthreads();
 }
 
-template <int ITEMS>
-__global__ __launch_bounds__(64) void encode_blocks(EncodeArgs a) {
+template <int ITEMS, bool FULL>
+__device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, uint32_t nb,
+                                             uint32_t* kvbuf, uint32_t* work) {
     constexpr uint32_t B = 64 * ITEMS;
-    constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
-    constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
-    constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
-    __shared__ __align__(16) uint32_t kvbuf[kKvWords];
-    __shared__ __align__(16) uint32_t work[kWorkWords];
-
     const uint32_t lane = threadIdx.x;
-    const uint32_t b = blockIdx.x;
     const uint64_t base = (uint64_t)b * B;
-    const uint32_t nb = (uint32_t)((a.n - base) < B ? (a.n - base) : B);
     const uint32_t F = a.F, K = a.K, KF = a.KF;
     uint32_t* __restrict__ rec = a.temp + (uint64_t)b * a.slot_words;
     const uint32_t cap = 1 + F * nb;  // raw record length
@@ -220,8 +238,10 @@ __global__ __launch_bounds__(64) void encode_blocks(EncodeArgs a) {
         sk[ax] = 0;
         lok[ax] = 0.0f;
         if ((uint32_t)ax < KF) {
-            lok[ax] = quantize_field<ITEMS>(a.x[ax], base, nb, lane, a.inv[ax], a.twoeb[ax],
-                                            a.eb[ax], qk[ax]);
+            float x[ITEMS];
+            load_block<ITEMS, FULL>(a.x[ax], base, nb, lane, x);
+            lok[ax] = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[ax], a.twoeb[ax], a.eb[ax],
+                                                  qk[ax]);
             uint32_t m = 0;
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) m = max(m, qk[ax][j] & 0xFFFFFFu);
@@ -244,7 +264,7 @@ __global__ __launch_bounds__(64) void encode_blocks(EncodeArgs a) {
             if ((uint32_t)ax < KF) key = (key << K) | ((qk[ax][j] & 0xFFFFFFu) >> sk[ax]);
         uint32_t i = lane * ITEMS + j;
         kv[j] = (key << 16) | i;
-        if (i < nb) keyor |= key;
+        if (FULL || i < nb) keyor |= key;
     }
     keyor = wave_or_u32(keyor);
 
@@ -252,36 +272,32 @@ __global__ __launch_bounds__(64) void encode_blocks(EncodeArgs a) {
     const uint32_t keybits = K * KF;
     for (uint32_t sh = 0; sh < keybits; sh += kDigitBits) {
         if (((keyor >> sh) & (kDigits - 1)) == 0) continue;  // identity pass
-        radix_pass<ITEMS>(kv, sh, nb, lane, work, kvbuf);
-    }
-    uint32_t key_s[ITEMS], idx_s[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        key_s[j] = kv[j] >> 16;
-        idx_s[j] = kv[j] & 0xFFFFu;
+        radix_pass<ITEMS, FULL>(kv, sh, nb, lane, work, kvbuf);
     }
 
     // ---- Stage 3 (Sec. 4.3): run-length coding of the sorted IDs
     uint32_t* uniq = work;
     uint32_t* start = work + B;
-    uint32_t prev = (uint32_t)__shfl_up((int)key_s[ITEMS - 1], 1);
-    uint32_t nflag = 0;
-    bool flag[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        uint32_t p = lane * ITEMS + j;
-        uint32_t before = j == 0 ? prev : key_s[j - 1];
-        flag[j] = (p < nb) && (p == 0 || key_s[j] != before);
-        nflag += flag[j];
-    }
-    uint32_t incl = wave_incl_scan_u32(nflag);
-    const uint32_t U = (uint32_t)__shfl((int)incl, 63);
+    uint32_t U;
     {
+        uint32_t prev = (uint32_t)__shfl_up((int)(kv[ITEMS - 1] >> 16), 1);
+        uint32_t nflag = 0;
+        bool flag[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t p = lane * ITEMS + j;
+            uint32_t key = kv[j] >> 16;
+            uint32_t before = j == 0 ? prev : (kv[j - 1] >> 16);
+            flag[j] = (FULL || p < nb) && (p == 0 || key != before);
+            nflag += flag[j];
+        }
+        uint32_t incl = wave_incl_scan_u32(nflag);
+        U = readlane(incl, 63);
         uint32_t k = incl - nflag;
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             if (flag[j]) {
-                uniq[k] = key_s[j];
+                uniq[k] = kv[j] >> 16;
                 start[k] = lane * ITEMS + j;
                 k++;
             }
@@ -290,109 +306,125 @@ __global__ __launch_bounds__(64) void encode_blocks(EncodeArgs a) {
     __syncthreads();
     if (lane == 0) start[U] = nb;
     __syncthreads();
-    // delta coding of the distinct IDs (stored as delta - 1) and counts - 1
-    uint32_t gap[ITEMS], cnt[ITEMS];
-    uint32_t gmax = 0, cmax = 0;
+    // delta coding of the distinct IDs (stored as delta - 1) and counts - 1:
+    // widths now, values again when they are packed
+    uint32_t w_gap, w_cnt;
+    {
+        uint32_t gmax = 0, cmax = 0;
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        uint32_t i = lane * ITEMS + j;
-        gap[j] = 0;
-        cnt[j] = 0;
-        if (i < U) {
-            uint32_t u = uniq[i];
-            uint32_t up = i ? uniq[i - 1] : 0xFFFFFFFFu;
-            gap[j] = u - up - 1u;
-            cnt[j] = start[i + 1] - start[i] - 1u;
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t i = lane * ITEMS + j;
+            if (i < U) {
+                uint32_t up = i ? uniq[i - 1] : 0xFFFFFFFFu;
+                gmax = max(gmax, uniq[i] - up - 1u);
+                cmax = max(cmax, start[i + 1] - start[i] - 1u);
+            }
         }
-        gmax = max(gmax, gap[j]);
-        cmax = max(cmax, cnt[j]);
+        w_gap = bit_width(wave_max_u32(gmax));
+        w_cnt = bit_width(wave_max_u32(cmax));
     }
-    const uint32_t w_gap = bit_width(wave_max_u32(gmax));
-    const uint32_t w_cnt = bit_width(wave_max_u32(cmax));
-    __syncthreads();
+    if (lane == 0) {
+        rec[0] = U << 2;
+        rec[1] = w_gap | (w_cnt << 5) | (sk[0] << 10) | (sk[1] << 15) | (sk[2] << 20);
+    }
 
+    // ---- arrays in record order: gaps, counts, then one section per field
     uint32_t pos = 2;
     bool over = false;
-    {
-        uint32_t gw = words_for(U, w_gap), cw = words_for(U, w_cnt);
-        if (pos + gw + cw > cap) {
-            over = true;
-        } else {
-            if (lane == 0) {
-                rec[0] = U << 2;
-                rec[1] = w_gap | (w_cnt << 5) | (sk[0] << 10) | (sk[1] << 15) | (sk[2] << 20);
+    for (uint32_t arr = 0; arr < 2 + F; arr++) {
+        uint32_t vals[ITEMS];
+        uint32_t w, count, nout = 0;
+        const uint32_t f = arr - 2;
+        if (arr < 2) {
+            count = U;
+            w = arr == 0 ? w_gap : w_cnt;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                uint32_t i = lane * ITEMS + j;
+                uint32_t v = 0;
+                if (i < U) {
+                    if (arr == 0) v = uniq[i] - (i ? uniq[i - 1] : 0xFFFFFFFFu) - 1u;
+                    else v = start[i + 1] - start[i] - 1u;
+                }
+                vals[j] = v;
             }
-            pack_store<ITEMS>(gap, U, w_gap, rec + pos, kvbuf, lane);
-            pack_store<ITEMS>(cnt, U, w_cnt, rec + pos + gw, kvbuf, lane);
-        }
-        pos += gw + cw;
-    }
-
-    // ---- per field: fixed-length payload in sorted order + outlier list
-    for (uint32_t f = 0; f < F && !over; f++) {
-        uint32_t q[ITEMS];
-        float lo;
-        uint32_t mask;
-        if (f < KF) {
-            // f is 0, 1 or 2 here; pick the registers without dynamic indexing
-#pragma unroll
-            for (int j = 0; j < ITEMS; j++) q[j] = f == 0 ? qk[0][j] : (f == 1 ? qk[1][j] : qk[2][j]);
-            lo = f == 0 ? lok[0] : (f == 1 ? lok[1] : lok[2]);
-            uint32_t s = f == 0 ? sk[0] : (f == 1 ? sk[1] : sk[2]);
-            mask = (1u << s) - 1u;
+            if (pos + words_for(count, w) > cap) {
+                over = true;
+                break;
+            }
+            __syncthreads();  // uniq/start reads done before `work` is reused
         } else {
-            lo = quantize_field<ITEMS>(a.x[f], base, nb, lane, a.inv[f], a.twoeb[f], a.eb[f], q);
-            mask = 0xFFFFFFu;
-        }
-        uint32_t vmax = 0, nout = 0;
+            uint32_t q[ITEMS];
+            float lo;
+            uint32_t mask;
+            if (f < KF) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            vmax = max(vmax, q[j] & mask);
-            nout += q[j] >> 31;
-        }
-        const uint32_t w = bit_width(wave_max_u32(vmax));
-        const uint32_t nout_all = wave_sum_u32(nout);
-        const uint32_t pw = words_for(nb, w);
-        const uint32_t sec = 2 + pw + 2 * nout_all;
-        if (pos + sec > cap) {
-            over = true;
-            break;
-        }
-        if (lane == 0) {
-            rec[pos] = f2u(lo);
-            rec[pos + 1] = w | (nout_all << 5);
-        }
-        // permute to sorted order through LDS
-        uint4* mine = reinterpret_cast<uint4*>(work + lane * (ITEMS + 4));
+                for (int j = 0; j < ITEMS; j++)
+                    q[j] = f == 0 ? qk[0][j] : (f == 1 ? qk[1][j] : qk[2][j]);
+                lo = f == 0 ? lok[0] : (f == 1 ? lok[1] : lok[2]);
+                const uint32_t s = f == 0 ? sk[0] : (f == 1 ? sk[1] : sk[2]);
+                mask = (1u << s) - 1u;
+            } else {
+                float x[ITEMS];
+                load_block<ITEMS, FULL>(a.x[f], base, nb, lane, x);
+                lo = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[f], a.twoeb[f], a.eb[f], q);
+                mask = 0xFFFFFFu;
+            }
+            uint32_t vmax = 0, no = 0;
 #pragma unroll
-        for (int k = 0; k < ITEMS / 4; k++)
-            mine[k] = make_uint4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
-        __syncthreads();
-        uint32_t qs[ITEMS], vs[ITEMS];
+            for (int j = 0; j < ITEMS; j++) {
+                vmax = max(vmax, q[j] & mask);
+                no += q[j] >> 31;
+            }
+            w = bit_width(wave_max_u32(vmax));
+            nout = wave_sum_u32(no);
+            count = nb;
+            if (pos + 2 + words_for(nb, w) + 2 * nout > cap) {
+                over = true;
+                break;
+            }
+            if (lane == 0) {
+                rec[pos] = f2u(lo);
+                rec[pos + 1] = w | (nout << 5);
+            }
+            pos += 2;
+            // permute to sorted order through LDS
+            uint4* mine = reinterpret_cast<uint4*>(work + lane * (ITEMS + 4));
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            qs[j] = (lane * ITEMS + j < nb) ? work[pad_addr<ITEMS>(idx_s[j])] : 0u;
-            vs[j] = qs[j] & mask;
+            for (int k = 0; k < ITEMS / 4; k++)
+                mine[k] = make_uint4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++)
+                vals[j] = (FULL || lane * ITEMS + j < nb)
+                              ? work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)] & mask
+                              : 0u;
         }
-        __syncthreads();
-        pack_store<ITEMS>(vs, nb, w, rec + pos + 2, kvbuf, lane);
-        if (nout_all) {
-            uint32_t c = 0;
+        pack_array<ITEMS>(vals, count, w, rec + pos, kvbuf, lane);
+        pos += words_for(count, w);
+        if (nout) {
+            // outlier flags of the sorted positions, read again from the staging
+            uint32_t flags = 0;
 #pragma unroll
-            for (int j = 0; j < ITEMS; j++) c += qs[j] >> 31;
+            for (int j = 0; j < ITEMS; j++)
+                if ((FULL || lane * ITEMS + j < nb) &&
+                    (work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)] >> 31))
+                    flags |= 1u << j;
+            const uint32_t c = __builtin_popcount(flags);
             uint32_t k = wave_incl_scan_u32(c) - c;
-            uint32_t* ol = rec + pos + 2 + pw;
+            uint32_t* ol = rec + pos;
             const float* xf = a.x[f] + base;
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) {
-                if (qs[j] >> 31) {
+                if ((flags >> j) & 1u) {
                     ol[2 * k] = lane * ITEMS + j;
-                    ol[2 * k + 1] = f2u(xf[idx_s[j]]);
+                    ol[2 * k + 1] = f2u(xf[kv[j] & 0xFFFFu]);
                     k++;
                 }
             }
+            pos += 2 * nout;
         }
-        pos += sec;
+        __syncthreads();  // staging reads done before the next field overwrites it
     }
 
     const bool raw = over || pos >= cap;
@@ -407,26 +439,52 @@ __global__ __launch_bounds__(64) void encode_blocks(EncodeArgs a) {
             for (uint32_t i = lane; i < nb; i += 64) dst[i] = f2u(xf[i]);
         }
     }
-    if (lane == 0) a.lens[b] = raw ? cap : pos;
+    if (lane == 0) {
+        const uint32_t len = raw ? cap : pos;
+        a.lens[b] = len;
+        atomicAdd(&a.supsum[b / kSuper], len);  // order-independent sum
+    }
     if (a.perm) {
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             uint32_t p = lane * ITEMS + j;
-            if (p < nb) a.perm[base + p] = (uint32_t)(base + (raw ? p : idx_s[j]));
+            if (FULL || p < nb) a.perm[base + p] = (uint32_t)(base + (raw ? p : (kv[j] & 0xFFFFu)));
         }
     }
+}
+
+template <int ITEMS, bool FULL>
+__global__ __launch_bounds__(64) void encode_blocks(EncodeArgs a, uint32_t first_block) {
+    constexpr uint32_t B = 64 * ITEMS;
+    constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
+    constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
+    constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
+    __shared__ __align__(16) uint32_t kvbuf[kKvWords];
+    __shared__ __align__(16) uint32_t work[kWorkWords];
+    const uint32_t b = first_block + blockIdx.x;
+    const uint64_t base = (uint64_t)b * B;
+    const uint32_t nb = (uint32_t)((a.n - base) < B ? (a.n - base) : B);
+    encode_block<ITEMS, FULL>(a, b, nb, kvbuf, work);
+}
+
+template <int ITEMS>
+void launch_encode_items(const EncodeArgs& a, hipStream_t s) {
+    // every block but a partial last one runs the bounds-check-free kernel
+    const uint32_t nfull = (uint32_t)(a.n / (64 * ITEMS));
+    if (nfull) hipLaunchKernelGGL((encode_blocks<ITEMS, true>), dim3(nfull), dim3(64), 0, s, a, 0u);
+    if (nfull < a.nblocks)
+        hipLaunchKernelGGL((encode_blocks<ITEMS, false>), dim3(1), dim3(64), 0, s, a, nfull);
 }
 
 }  // namespace
 
 hipError_t launch_encode(const EncodeArgs& a, hipStream_t s) {
     if (a.nblocks == 0) return hipSuccess;
-    dim3 grid(a.nblocks), block(64);
     switch (a.B) {
-        case 256: hipLaunchKernelGGL(encode_blocks<4>, grid, block, 0, s, a); break;
-        case 512: hipLaunchKernelGGL(encode_blocks<8>, grid, block, 0, s, a); break;
-        case 1024: hipLaunchKernelGGL(encode_blocks<16>, grid, block, 0, s, a); break;
-        case 2048: hipLaunchKernelGGL(encode_blocks<32>, grid, block, 0, s, a); break;
+        case 256: launch_encode_items<4>(a, s); break;
+        case 512: launch_encode_items<8>(a, s); break;
+        case 1024: launch_encode_items<16>(a, s); break;
+        case 2048: launch_encode_items<32>(a, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -41,22 +41,23 @@ struct EncodeArgs {
     uint32_t slot_words;  // record slot stride in the workspace (>= 1 + F*B)
     uint32_t* temp;       // nblocks record slots
     uint32_t* lens;       // record length (words) per block
+    uint32_t* supsum;     // per 64-block superblock: sum of record lengths (zeroed before)
     uint32_t* perm;       // nullable: n global input indices
 };
 
 struct ScanArgs {
-    const uint32_t* lens;
-    uint64_t* offs;        // exclusive prefix of lens (words, inside the record area)
-    uint64_t* total_bytes; // whole stream size in bytes
-    uint64_t* ext_bytes;   // nullable second destination of the size (async API)
-    uint32_t nblocks;
-    uint64_t prefix;       // words before the record area
+    const uint32_t* supsum; // record words per superblock
+    uint64_t* supoff;       // exclusive prefix of supsum (words, inside the record area)
+    uint64_t* total_bytes;  // whole stream size in bytes
+    uint64_t* ext_bytes;    // nullable second destination of the size (async API)
+    uint32_t nsuper;
+    uint64_t prefix;        // words before the record area
 };
 
 struct CopyArgs {
     const uint32_t* temp;
     const uint32_t* lens;
-    const uint64_t* offs;
+    const uint64_t* supoff;
     const uint64_t* total_bytes;
     uint32_t* out;
     uint64_t capacity;     // bytes
@@ -80,52 +81,90 @@ struct DecodeArgs {
 };
 
 // ------------------------------------------------------------ wave64 primitives
+// Cross-lane traffic uses DPP (no LDS round trip): quad_perm / row mirrors
+// inside 16-lane rows, row_shr / row_bcast for scans, and v_readlane to
+// combine the four rows into a wave-uniform (SGPR) result.  Callers keep all
+// 64 lanes active.
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
-    return v;
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kQuadSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kQuadSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
 
-__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v |= (uint32_t)__shfl_xor((int)v, o);
-    return v;
-}
+// Reduce within 16-lane rows (every lane of a row gets the row result), then
+// across the four rows through readlane.
+#define GPZ_WAVE_REDUCE(NAME, T, OP, TOBITS, FROMBITS)                         \
+    __device__ __forceinline__ T NAME(T v) {                                   \
+        v = OP(v, FROMBITS(dpp<kQuadSwap1>(TOBITS(v))));                       \
+        v = OP(v, FROMBITS(dpp<kQuadSwap2>(TOBITS(v))));                       \
+        v = OP(v, FROMBITS(dpp<kRowHalfMirror>(TOBITS(v))));                   \
+        v = OP(v, FROMBITS(dpp<kRowMirror>(TOBITS(v))));                       \
+        T r0 = FROMBITS(readlane(TOBITS(v), 0)), r1 = FROMBITS(readlane(TOBITS(v), 16)); \
+        T r2 = FROMBITS(readlane(TOBITS(v), 32)), r3 = FROMBITS(readlane(TOBITS(v), 48)); \
+        return OP(OP(r0, r1), OP(r2, r3));                                     \
+    }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
-    return v;
-}
+__device__ __forceinline__ uint32_t op_max(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint32_t op_or(uint32_t a, uint32_t b) { return a | b; }
+__device__ __forceinline__ uint32_t op_add(uint32_t a, uint32_t b) { return a + b; }
+__device__ __forceinline__ float op_fmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ uint32_t id_u32(uint32_t v) { return v; }
+__device__ __forceinline__ uint32_t f_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ float bits_f(uint32_t v) { return __uint_as_float(v); }
 
-__device__ __forceinline__ float wave_min_f32(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
-}
+GPZ_WAVE_REDUCE(wave_max_u32, uint32_t, op_max, id_u32, id_u32)
+GPZ_WAVE_REDUCE(wave_or_u32, uint32_t, op_or, id_u32, id_u32)
+GPZ_WAVE_REDUCE(wave_sum_u32, uint32_t, op_add, id_u32, id_u32)
+GPZ_WAVE_REDUCE(wave_min_f32, float, op_fmin, f_bits, bits_f)
+#undef GPZ_WAVE_REDUCE
 
 // Inclusive prefix sum across the wave (lane order).
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = (uint32_t)__shfl_up((int)v, o);
-        if (lane >= (uint32_t)o) v += t;
-    }
+    const uint32_t lane = lane_id(), rl = lane & 15u;
+    uint32_t t;
+    t = dpp<kRowShr1>(v);
+    v += rl >= 1 ? t : 0u;
+    t = dpp<kRowShr2>(v);
+    v += rl >= 2 ? t : 0u;
+    t = dpp<kRowShr4>(v);
+    v += rl >= 4 ? t : 0u;
+    t = dpp<kRowShr8>(v);
+    v += rl >= 8 ? t : 0u;
+    t = dpp<kRowBcast15>(v);
+    v += (lane & 16u) ? t : 0u;
+    t = dpp<kRowBcast31>(v);
+    v += lane >= 32 ? t : 0u;
     return v;
 }
 
 // Inclusive prefix maximum across the wave (lane order).
 __device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = (uint32_t)__shfl_up((int)v, o);
-        if (lane >= (uint32_t)o) v = max(v, t);
-    }
+    const uint32_t lane = lane_id(), rl = lane & 15u;
+    uint32_t t;
+    t = dpp<kRowShr1>(v);
+    v = rl >= 1 ? max(v, t) : v;
+    t = dpp<kRowShr2>(v);
+    v = rl >= 2 ? max(v, t) : v;
+    t = dpp<kRowShr4>(v);
+    v = rl >= 4 ? max(v, t) : v;
+    t = dpp<kRowShr8>(v);
+    v = rl >= 8 ? max(v, t) : v;
+    t = dpp<kRowBcast15>(v);
+    v = (lane & 16u) ? max(v, t) : v;
+    t = dpp<kRowBcast31>(v);
+    v = lane >= 32 ? max(v, t) : v;
     return v;
 }
 
