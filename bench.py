@@ -39,11 +39,20 @@ def main():
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--cpu-sample-blocks", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--form", choices=["plain", "batched", "serving"], default="plain",
+                    help="plain per-snapshot launch (default), batched snapshots, or serving loop")
+    ap.add_argument("--jobs", type=int, default=256, help="snapshots of the batched form")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the compressor is single-GPU (blocks are independent; "
               "see the sharding notes in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.form == "batched":
+        return bench_batched(args)
+    if args.form == "serving":
+        import serve_bench
+        return serve_bench.main(args)
 
     import torch
 
@@ -173,6 +182,117 @@ def main():
                              "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3)},
     }
     print(json.dumps(rec), flush=True)
+
+
+def bench_batched(args):
+    """Batched form: snapshots of uneven sizes (log-uniform 10K..8M particles,
+    3-6 fields, 8-1024 clusters, abs eb log-uniform 1e-5..1e-2) compressed and
+    decompressed by the persistent batched kernels under a HIP graph, with the
+    launch geometry picked by the autotuner, against a loop of plain
+    per-snapshot launches of the same jobs."""
+    import torch
+
+    import paper_2508_10305_amd as gpz
+    from paper_2508_10305_amd import autotune, synth
+    from paper_2508_10305_amd.batch import Batch, default_config
+
+    specs = synth.batch_specs(args.jobs, seed=4)
+    t0 = time.time()
+    fields = [synth.clusters_device(sp["n"], sp["seed"], sp["clusters"],
+                                    extra_fields=sp["fields"] - 3) for sp in specs]
+    torch.cuda.synchronize()
+    S = sum(4 * sp["n"] * sp["fields"] for sp in specs)
+    log(f"[bench] batched: {len(specs)} snapshots, {sum(sp['n'] for sp in specs)} particles, "
+        f"{S / 1e9:.2f} GB, generated in {time.time() - t0:.1f}s")
+    ebs = [sp["eb"] for sp in specs]
+    p = gpz.params(3)
+    outs = [torch.empty(gpz.max_compressed_bytes(sp["n"], sp["fields"], p), dtype=torch.uint8,
+                        device="cuda") for sp in specs]
+    decs = [[torch.empty(sp["n"], dtype=torch.float32, device="cuda") for _ in range(sp["fields"])]
+            for sp in specs]
+
+    # plain per-snapshot loop on the same jobs
+    comps = [gpz.Compressor(sp["n"], sp["fields"], p) for sp in specs]
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def plain_round():
+        for j, sp in enumerate(specs):
+            comps[j].compress_async(fields[j], ebs[j])
+            gpz.decompress_async(comps[j].out, sp["n"], sp["fields"], decs[j], err, p)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_plain = timed(plain_round, max(1, args.steps // 4))
+    ref = [c.out for c in comps]
+    ref_sizes = []
+    for j, sp in enumerate(specs):
+        s_, _ = comps[j].compress(fields[j], ebs[j])
+        ref_sizes.append(int(s_.numel()))
+    del comps
+
+    ws = torch.empty(Batch.workspace_bytes(fields, ebs, outs, decs, p), dtype=torch.uint8,
+                     device="cuda")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def run(grid, tile):
+        cfg = default_config()
+        cfg.grid, cfg.tile, cfg.use_graph = grid, tile, 1
+        b = Batch(fields, ebs, outs, dec=decs, p=p, config=cfg, workspace=ws)
+
+        def rnd():
+            b.compress()
+            b.decompress()
+        ms = timed(rnd, 3)
+        b.close()
+        return ms
+
+    total_blocks = sum((sp["n"] + 1023) // 1024 for sp in specs)
+    key = autotune.shape_key(torch.cuda.get_device_name(0), 1024, total_blocks, len(specs))
+    tuned = autotune.tune(run, cus, key, use_cache=False, log=log)
+    cfg = default_config()
+    cfg.grid, cfg.tile, cfg.use_graph = tuned["grid"], tuned["tile"], 1
+    b = Batch(fields, ebs, outs, dec=decs, p=p, config=cfg, workspace=ws)
+
+    def rnd():
+        b.compress()
+        b.decompress()
+    ms_batch = timed(rnd, args.steps)
+    sizes = b.sizes()
+    assert (b.errors() == 0).all()
+    same = all(int(sizes[j]) == ref_sizes[j] and
+               bool(torch.equal(outs[j][: ref_sizes[j]], ref[j][: ref_sizes[j]]))
+               for j in range(len(specs)))
+    C = int(sizes.sum())
+    rec = {
+        "metric": "batched compress+decompress GB/s (persistent fused kernels under a HIP graph)",
+        "form": "batched",
+        "value": round(2 * S / (ms_batch * 1e-3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "ms_per_step": round(ms_batch, 4),
+        "plain_loop_ms": round(ms_plain, 4),
+        "plain_loop_GBps": round(2 * S / (ms_plain * 1e-3) / 1e9, 2),
+        "speedup_vs_plain_loop": round(ms_plain / ms_batch, 3),
+        "streams_identical_to_plain": same,
+        "compression_ratio": round(S / C, 4),
+        "autotune": {"grid": tuned["grid"], "tile": tuned["tile"], "table": tuned["table"]},
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(specs)} snapshots, particles log-uniform 10K-8M, 3-6 float32 "
+                               "fields, abs eb log-uniform 1e-5..1e-2", "bytes": S},
+    }
+    print(json.dumps(rec), flush=True)
+    b.close()
 
 
 if __name__ == "__main__":

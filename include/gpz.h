@@ -147,6 +147,70 @@ typedef struct {
 } gpz_info;
 int gpz_inspect(const void *h_prefix, uint64_t bytes, gpz_info *out);
 
+/* ---------------------------------------------------------------- batches
+ * Batched form: many snapshots of uneven sizes, compressed or decompressed by
+ * persistent kernels that take blocks from a device work queue (one launch
+ * per stage for the whole batch), optionally captured once into a HIP graph
+ * and replayed.  Each job's stream is byte-identical to gpz_compress of that
+ * snapshot alone.  The batch owns small device tables (allocated once by
+ * gpz_batch_create); the caller owns inputs, outputs and the workspace. */
+
+typedef struct {
+    const float *const *fields; /* host array of F device pointers: compression input
+                                   (NULL for a job that is only decompressed) */
+    uint64_t n;                 /* particles */
+    uint32_t nfields;           /* F, 1..64 */
+    const float *eb;            /* host array of F absolute bounds (as for gpz_compress) */
+    void *out;                  /* device stream buffer: written by compression, read by
+                                   decompression */
+    uint64_t out_capacity;      /* bytes; must be >= gpz_max_compressed_bytes(n, F, p) */
+    float *const *dec_fields;   /* host array of F device pointers: decompression output
+                                   (NULL for a job that is only compressed) */
+} gpz_job;
+
+typedef struct {
+    uint32_t grid;       /* persistent workgroups (one wave each); default 8 per CU */
+    uint32_t tile;       /* consecutive blocks taken per work-queue grab; default 1 */
+    uint32_t use_graph;  /* 1: capture the kernel sequence once, then replay it */
+    uint32_t max_jobs;   /* capacity for gpz_batch_rebind (0: the creation job count) */
+    uint64_t max_blocks; /* capacity in blocks over all jobs (0: at creation) */
+} gpz_batch_config;
+
+typedef struct gpz_batch gpz_batch;
+
+/* Fills *c with the defaults (queries the current device's CU count). */
+void gpz_default_batch_config(gpz_batch_config *c);
+
+/* Device workspace for a job list (record slots of every block); 0 on
+ * invalid jobs.  All jobs share the parameters p (NULL = defaults). */
+uint64_t gpz_batch_workspace_bytes(const gpz_job *jobs, uint32_t njobs, const gpz_params *p);
+
+/* Creates a batch bound to `jobs` and the caller's workspace d_ws (device,
+ * >= gpz_batch_workspace_bytes).  Allocates the batch's device tables and a
+ * private non-blocking stream used for graph capture.  *out = NULL on error. */
+int gpz_batch_create(gpz_batch **out, const gpz_job *jobs, uint32_t njobs, const gpz_params *p,
+                     const gpz_batch_config *cfg, void *d_ws, uint64_t ws_bytes);
+
+/* Binds the batch to a new job list within its capacities, without device
+ * allocation and without invalidating captured graphs.  Synchronizes
+ * `stream` first (earlier work of this batch must have finished). */
+int gpz_batch_rebind(gpz_batch *b, const gpz_job *jobs, uint32_t njobs, void *d_ws,
+                     uint64_t ws_bytes, void *stream);
+
+/* Enqueues compression of every job on `stream` (no host synchronization).
+ * Stream sizes land in the device array gpz_batch_sizes(b)[job].  Every job
+ * must have input fields. */
+int gpz_batch_compress(gpz_batch *b, void *stream);
+
+/* Enqueues decompression of every job's `out` stream into its dec_fields
+ * (no host synchronization).  A malformed stream sets
+ * gpz_batch_errors(b)[job] (device uint32) nonzero. */
+int gpz_batch_decompress(gpz_batch *b, void *stream);
+
+const uint64_t *gpz_batch_sizes(const gpz_batch *b);
+const uint32_t *gpz_batch_errors(const gpz_batch *b);
+int gpz_batch_destroy(gpz_batch *b);
+
 /* Optional kernel timing with HIP events recorded on the launch stream.
  * While enabled (per host thread), every compress / decompress call records
  * an event pair around each of its kernels.  gpz_timing_collect waits for

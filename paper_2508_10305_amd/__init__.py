@@ -24,7 +24,9 @@ EXPORTS = (
     "gpz_default_params", "gpz_max_compressed_bytes", "gpz_compress_workspace_bytes",
     "gpz_decompress_workspace_bytes", "gpz_compress", "gpz_compress_async", "gpz_decompress",
     "gpz_decompress_async", "gpz_bound_check", "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
-    "gpz_set_timing", "gpz_timing_collect", "gpz_strerror",
+    "gpz_set_timing", "gpz_timing_collect", "gpz_strerror", "gpz_default_batch_config",
+    "gpz_batch_workspace_bytes", "gpz_batch_create", "gpz_batch_rebind", "gpz_batch_compress",
+    "gpz_batch_decompress", "gpz_batch_sizes", "gpz_batch_errors", "gpz_batch_destroy",
 )
 
 
@@ -42,6 +44,18 @@ class GpzError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_uint32), ("seg_bits", ctypes.c_uint32),
                 ("key_fields", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("fields", ctypes.c_void_p), ("n", ctypes.c_uint64), ("nfields", ctypes.c_uint32),
+                ("eb", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("out_capacity", ctypes.c_uint64), ("dec_fields", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_uint32), ("tile", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32), ("max_jobs", ctypes.c_uint32),
+                ("max_blocks", ctypes.c_uint64)]
 
 
 class Info(ctypes.Structure):
@@ -94,6 +108,25 @@ def _lib():
         L.gpz_timing_collect.restype = ctypes.c_int
         L.gpz_strerror.argtypes = [ctypes.c_int]
         L.gpz_strerror.restype = ctypes.c_char_p
+        jp, cp = ctypes.POINTER(Job), ctypes.POINTER(BatchConfig)
+        L.gpz_default_batch_config.argtypes = [cp]
+        L.gpz_default_batch_config.restype = None
+        L.gpz_batch_workspace_bytes.argtypes = [jp, u32, pp]
+        L.gpz_batch_workspace_bytes.restype = u64
+        L.gpz_batch_create.argtypes = [ctypes.POINTER(vp), jp, u32, pp, cp, vp, u64]
+        L.gpz_batch_create.restype = ctypes.c_int
+        L.gpz_batch_rebind.argtypes = [vp, jp, u32, vp, u64, vp]
+        L.gpz_batch_rebind.restype = ctypes.c_int
+        L.gpz_batch_compress.argtypes = [vp, vp]
+        L.gpz_batch_compress.restype = ctypes.c_int
+        L.gpz_batch_decompress.argtypes = [vp, vp]
+        L.gpz_batch_decompress.restype = ctypes.c_int
+        L.gpz_batch_sizes.argtypes = [vp]
+        L.gpz_batch_sizes.restype = vp
+        L.gpz_batch_errors.argtypes = [vp]
+        L.gpz_batch_errors.restype = vp
+        L.gpz_batch_destroy.argtypes = [vp]
+        L.gpz_batch_destroy.restype = ctypes.c_int
         _LIB = L
     return _LIB
 

@@ -132,6 +132,7 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     CompressWs w = layout(n, F, B, ws);
 
     EncodeArgs ea{};
+    ScanArgs sa{};
     CopyArgs ca{};
     for (uint32_t f = 0; f < F; f++) {
         ea.x[f] = n ? h_fields[f] : nullptr;
@@ -140,7 +141,7 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
         ea.inv[f] = 1.0f / ea.twoeb[f];
         uint32_t bits;
         memcpy(&bits, &h_eb[f], 4);
-        ca.eb_bits[f] = bits;
+        sa.eb_bits[f] = bits;
     }
     ea.n = n;
     ea.F = F;
@@ -154,13 +155,20 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     ea.supsum = w.supsum;
     ea.perm = d_perm;
 
-    ScanArgs sa{};
     sa.supsum = w.supsum;
     sa.supoff = w.supoff;
     sa.total_bytes = w.total;
     sa.ext_bytes = d_out_bytes;
     sa.nsuper = (uint32_t)nsuper_of(nb);
     sa.prefix = prefix_words(n, F, B);
+    sa.out = static_cast<uint32_t*>(d_out);
+    sa.capacity = cap;
+    sa.n = n;
+    sa.F = F;
+    sa.B = B;
+    sa.K = p.seg_bits;
+    sa.KF = p.key_fields;
+    sa.nblocks = (uint32_t)nb;
 
     ca.temp = w.temp;
     ca.lens = w.lens;
@@ -170,11 +178,7 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     ca.capacity = cap;
     ca.slot_words = w.slot_words;
     ca.nblocks = (uint32_t)nb;
-    ca.n = n;
     ca.F = F;
-    ca.B = B;
-    ca.K = p.seg_bits;
-    ca.KF = p.key_fields;
 
     Timer tm(s);
     int rc = to_status(launch_fill_u32(w.supsum, 0u, nsuper_of(nb), s));

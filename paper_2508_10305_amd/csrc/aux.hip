@@ -12,9 +12,10 @@ constexpr uint32_t kScanThreads = 1024;
 
 // Exclusive scan of the per-superblock record sizes (one workgroup; there
 // are only ceil(nblocks / 64) of them): thread t sums a contiguous chunk, the
-// chunk totals are scanned in LDS, then each thread writes its offsets.
-__global__ __launch_bounds__(kScanThreads) void scan_lengths(ScanArgs a) {
-    __shared__ uint64_t part[kScanThreads];
+// chunk totals are scanned in LDS, then each thread writes its offsets.  The
+// last thread publishes the stream size; when the stream fits the output
+// buffer the workgroup also writes the header and the eb table.
+__device__ __forceinline__ void scan_body(const ScanArgs& a, uint64_t* part) {
     const uint32_t t = threadIdx.x;
     const uint32_t ns = a.nsuper;
     const uint32_t chunk = (ns + kScanThreads - 1) / kScanThreads;
@@ -35,29 +36,13 @@ __global__ __launch_bounds__(kScanThreads) void scan_lengths(ScanArgs a) {
         a.supoff[i] = run;
         run += a.supsum[i];
     }
+    const uint64_t bytes = 4 * (a.prefix + part[kScanThreads - 1]);
     if (t == kScanThreads - 1) {
-        uint64_t bytes = 4 * (a.prefix + part[t]);
         *a.total_bytes = bytes;
         if (a.ext_bytes) *a.ext_bytes = bytes;
     }
-}
-
-// One wave per block record: copy it from its slot to prefix + offs[b], and
-// write its length-table entry (and the superblock entry every 64 blocks).
-// Block 0 also writes the header and the eb table.  Nothing is written when
-// the stream does not fit the output buffer.
-__global__ __launch_bounds__(256) void copy_records(CopyArgs a) {
-    const uint64_t total = *a.total_bytes;
-    if (total > a.capacity) return;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const uint64_t nsup = nsuper_of(a.nblocks);
-    uint32_t* sup = a.out + kHeaderWords;
-    uint32_t* ebt = sup + 2 * nsup;
-    uint32_t* lt = ebt + a.F;
-    uint32_t* recs = lt + a.nblocks;
-    if (b == 0) {
-        if (lane == 0) {
+    if (bytes <= a.capacity) {
+        if (t == 0) {
             a.out[0] = kMagic;
             a.out[1] = kVersion;
             a.out[2] = (uint32_t)(a.n & 0xFFFFFFFFu);
@@ -67,10 +52,37 @@ __global__ __launch_bounds__(256) void copy_records(CopyArgs a) {
             a.out[6] = a.K | (a.KF << 8);
             a.out[7] = a.nblocks;
         }
-        for (uint32_t f = lane; f < a.F; f += 64) ebt[f] = a.eb_bits[f];
+        uint32_t* ebt = a.out + kHeaderWords + 2 * nsuper_of(a.nblocks);
+        for (uint32_t f = t; f < a.F; f += kScanThreads) ebt[f] = a.eb_bits[f];
     }
-    if (b >= a.nblocks) return;
-    // offset = superblock offset + lengths of the earlier blocks of the superblock
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_lengths(ScanArgs a) {
+    __shared__ uint64_t part[kScanThreads];
+    scan_body(a, part);
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_lengths_batch(const ScanArgs* jobs,
+                                                                    const BatchLaunch* L) {
+    __shared__ uint64_t part[kScanThreads];
+    const uint32_t njobs = L->njobs;
+    for (uint32_t j = blockIdx.x; j < njobs; j += gridDim.x) {
+        scan_body(jobs[j], part);
+        __syncthreads();
+    }
+}
+
+// One wave per block record: copy it from its slot to its final offset
+// (superblock offset + lengths of the earlier blocks of the superblock), and
+// write its length-table entry (and the superblock entry every 64 blocks).
+// Nothing is written when the stream does not fit the output buffer.
+__device__ __forceinline__ void copy_body(const CopyArgs& a, uint32_t b, uint32_t lane) {
+    const uint64_t total = *a.total_bytes;
+    if (total > a.capacity) return;
+    const uint64_t nsup = nsuper_of(a.nblocks);
+    uint32_t* sup = a.out + kHeaderWords;
+    uint32_t* lt = sup + 2 * nsup + a.F;
+    uint32_t* recs = lt + a.nblocks;
     const uint32_t sb = b / kSuper, first = sb * kSuper;
     const uint32_t before = wave_sum_u32(first + lane < b ? a.lens[first + lane] : 0u);
     const uint32_t len = a.lens[b];
@@ -78,13 +90,29 @@ __global__ __launch_bounds__(256) void copy_records(CopyArgs a) {
     if (lane == 0) {
         lt[b] = len;
         if (b % kSuper == 0) {
-            sup[2 * (b / kSuper)] = (uint32_t)(off & 0xFFFFFFFFu);
-            sup[2 * (b / kSuper) + 1] = (uint32_t)(off >> 32);
+            sup[2 * sb] = (uint32_t)(off & 0xFFFFFFFFu);
+            sup[2 * sb + 1] = (uint32_t)(off >> 32);
         }
     }
     const uint32_t* src = a.temp + (uint64_t)b * a.slot_words;
     uint32_t* dst = recs + off;
     for (uint32_t k = lane; k < len; k += 64) dst[k] = src[k];
+}
+
+__global__ __launch_bounds__(256) void copy_records(CopyArgs a) {
+    const uint32_t b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= a.nblocks) return;
+    copy_body(a, b, threadIdx.x & 63u);
+}
+
+__global__ __launch_bounds__(256) void copy_records_batch(const CopyArgs* jobs,
+                                                          const BatchLaunch* L) {
+    const uint32_t total = L->total_blocks, njobs = L->njobs;
+    const uint32_t* prefix = L->block_prefix;
+    for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < total; g += gridDim.x * 4) {
+        const uint32_t j = find_job(prefix, njobs, g);
+        copy_body(jobs[j], g - prefix[j], threadIdx.x & 63u);
+    }
 }
 
 __global__ void fill_u32(uint32_t* p, uint32_t value, uint64_t count) {
@@ -204,9 +232,21 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_copy(const CopyArgs& a, hipStream_t s) {
-    uint32_t groups = (a.nblocks + 3) / 4;
-    if (groups == 0) groups = 1;
+    if (a.nblocks == 0) return hipSuccess;
+    const uint32_t groups = (a.nblocks + 3) / 4;
     hipLaunchKernelGGL(copy_records, dim3(groups), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_batch(const ScanArgs* jobs, const BatchLaunch* L, const BatchShape& S,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(scan_lengths_batch, dim3(S.scan_grid), dim3(kScanThreads), 0, s, jobs, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_batch(const CopyArgs* jobs, const BatchLaunch* L, const BatchShape& S,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(copy_records_batch, dim3(S.copy_grid), dim3(256), 0, s, jobs, L);
     return hipGetLastError();
 }
 

@@ -51,20 +51,28 @@ __device__ __forceinline__ uint32_t extract(const uint32_t* __restrict__ words, 
 __device__ __forceinline__ uint32_t low_mask(uint32_t w) { return w >= 32u ? ~0u : ((1u << w) - 1u); }
 
 template <int ITEMS>
-__global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
+struct DecodeSmem {
+    static constexpr uint32_t B = 64 * ITEMS;
+    // widest coded arrays: payload 24 bits/value; gaps 15 + counts 12 bits
+    static constexpr uint32_t kPay = (B * 24) / 32 + 2;
+    static constexpr uint32_t kRle = (B * 15) / 32 + (B * 12) / 32 + 4;
+    static constexpr uint32_t kWords = ((kPay > kRle ? kPay : kRle) + 3) & ~3u;  // 16-byte multiple
+    static constexpr uint32_t kPadB = 64 * (ITEMS + 4);
+    uint32_t words[kWords];
+    uint32_t keys[kPadB];
+    uint32_t ystage[B];
+};
+
+template <int ITEMS>
+__device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
+                                             DecodeSmem<ITEMS>& sm) {
     constexpr uint32_t B = 64 * ITEMS;
     constexpr uint32_t G = ITEMS / 4;  // 16-byte groups per lane
-    // widest coded arrays: payload 24 bits/value; gaps 15 + counts 12 bits
-    constexpr uint32_t kPay = (B * 24) / 32 + 2;
-    constexpr uint32_t kRle = (B * 15) / 32 + (B * 12) / 32 + 4;
-    constexpr uint32_t kWords = kPay > kRle ? kPay : kRle;
-    constexpr uint32_t kPadB = 64 * (ITEMS + 4);
-    __shared__ __align__(16) uint32_t words[kWords];
-    __shared__ __align__(16) uint32_t keys[kPadB];
-    __shared__ __align__(16) uint32_t ystage[B];
+    uint32_t* words = sm.words;
+    uint32_t* keys = sm.keys;
+    uint32_t* ystage = sm.ystage;
 
     const uint32_t lane = threadIdx.x;
-    const uint32_t b = blockIdx.x;
     const uint64_t base = (uint64_t)b * B;
     const uint32_t nb = (uint32_t)((a.n - base) < B ? (a.n - base) : B);
     const uint32_t F = a.F, K = a.K, KF = a.KF;
@@ -307,7 +315,48 @@ __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
     }
 }
 
+template <int ITEMS>
+__global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
+    __shared__ __align__(16) DecodeSmem<ITEMS> sm;
+    decode_block<ITEMS>(a, blockIdx.x, sm);
+}
+
+// Persistent decoder over the blocks of many streams: each wave takes `tile`
+// consecutive blocks from a device work queue until the queue is empty.
+template <int ITEMS>
+__global__ __launch_bounds__(64) void decode_batch(const DecodeArgs* __restrict__ jobs,
+                                                   const BatchLaunch* __restrict__ L) {
+    __shared__ __align__(16) DecodeSmem<ITEMS> sm;
+    const uint32_t total = L->total_blocks, njobs = L->njobs, tile = L->tile;
+    const uint32_t* prefix = L->block_prefix;
+    for (;;) {
+        uint32_t item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(L->counter + 1, tile);
+        item = (uint32_t)__shfl((int)item, 0);
+        if (item >= total) break;
+        const uint32_t end = min(item + tile, total);
+        for (uint32_t g = item; g < end; g++) {
+            const uint32_t j = find_job(prefix, njobs, g);
+            decode_block<ITEMS>(jobs[j], g - prefix[j], sm);
+            __syncthreads();
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_decode_batch(const DecodeArgs* jobs, const BatchLaunch* L,
+                               const BatchShape& S, hipStream_t s) {
+    dim3 grid(S.grid), block(64);
+    switch (S.B) {
+        case 256: hipLaunchKernelGGL(decode_batch<4>, grid, block, 0, s, jobs, L); break;
+        case 512: hipLaunchKernelGGL(decode_batch<8>, grid, block, 0, s, jobs, L); break;
+        case 1024: hipLaunchKernelGGL(decode_batch<16>, grid, block, 0, s, jobs, L); break;
+        case 2048: hipLaunchKernelGGL(decode_batch<32>, grid, block, 0, s, jobs, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t s) {
     if (a.nblocks == 0) return hipSuccess;

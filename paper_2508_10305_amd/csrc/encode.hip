@@ -476,7 +476,73 @@ void launch_encode_items(const EncodeArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((encode_blocks<ITEMS, false>), dim3(1), dim3(64), 0, s, a, nfull);
 }
 
+// Persistent encoder over the full blocks of many snapshots: each wave takes
+// `tile` consecutive blocks from a device work queue until it is empty.
+template <int ITEMS>
+__global__ __launch_bounds__(64) void encode_batch(const EncodeArgs* __restrict__ jobs,
+                                                   const BatchLaunch* __restrict__ L) {
+    constexpr uint32_t B = 64 * ITEMS;
+    constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
+    constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
+    constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
+    __shared__ __align__(16) uint32_t kvbuf[kKvWords];
+    __shared__ __align__(16) uint32_t work[kWorkWords];
+    const uint32_t total = L->total_full, njobs = L->njobs, tile = L->tile;
+    const uint32_t* prefix = L->full_prefix;
+    for (;;) {
+        uint32_t item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(L->counter, tile);
+        item = (uint32_t)__shfl((int)item, 0);
+        if (item >= total) break;
+        const uint32_t end = min(item + tile, total);
+        for (uint32_t g = item; g < end; g++) {
+            const uint32_t j = find_job(prefix, njobs, g);
+            encode_block<ITEMS, true>(jobs[j], g - prefix[j], B, kvbuf, work);
+            __syncthreads();
+        }
+    }
+}
+
+// The partial last block of each snapshot that has one.
+template <int ITEMS>
+__global__ __launch_bounds__(64) void encode_batch_tails(const EncodeArgs* __restrict__ jobs,
+                                                         const BatchLaunch* __restrict__ L) {
+    constexpr uint32_t B = 64 * ITEMS;
+    constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
+    constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
+    constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
+    __shared__ __align__(16) uint32_t kvbuf[kKvWords];
+    __shared__ __align__(16) uint32_t work[kWorkWords];
+    const uint32_t ntail = L->ntail;
+    for (uint32_t t = blockIdx.x; t < ntail; t += gridDim.x) {
+        const EncodeArgs& a = jobs[L->tail_jobs[t]];
+        const uint32_t b = a.nblocks - 1;
+        const uint32_t nb = (uint32_t)(a.n - (uint64_t)b * B);
+        encode_block<ITEMS, false>(a, b, nb, kvbuf, work);
+        __syncthreads();
+    }
+}
+
+template <int ITEMS>
+void launch_encode_batch_items(const EncodeArgs* jobs, const BatchLaunch* L, const BatchShape& S,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(encode_batch<ITEMS>, dim3(S.grid), dim3(64), 0, s, jobs, L);
+    hipLaunchKernelGGL(encode_batch_tails<ITEMS>, dim3(S.tail_grid), dim3(64), 0, s, jobs, L);
+}
+
 }  // namespace
+
+hipError_t launch_encode_batch(const EncodeArgs* jobs, const BatchLaunch* L, const BatchShape& S,
+                               hipStream_t s) {
+    switch (S.B) {
+        case 256: launch_encode_batch_items<4>(jobs, L, S, s); break;
+        case 512: launch_encode_batch_items<8>(jobs, L, S, s); break;
+        case 1024: launch_encode_batch_items<16>(jobs, L, S, s); break;
+        case 2048: launch_encode_batch_items<32>(jobs, L, S, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_encode(const EncodeArgs& a, hipStream_t s) {
     if (a.nblocks == 0) return hipSuccess;

@@ -52,6 +52,12 @@ struct ScanArgs {
     uint64_t* ext_bytes;    // nullable second destination of the size (async API)
     uint32_t nsuper;
     uint64_t prefix;        // words before the record area
+    // stream header, written here when the stream fits the output buffer
+    uint32_t* out;
+    uint64_t capacity;      // bytes
+    uint64_t n;
+    uint32_t F, B, K, KF, nblocks;
+    uint32_t eb_bits[kMaxFields];
 };
 
 struct CopyArgs {
@@ -63,9 +69,7 @@ struct CopyArgs {
     uint64_t capacity;     // bytes
     uint32_t slot_words;
     uint32_t nblocks;
-    uint64_t n;
-    uint32_t F, B, K, KF;
-    uint32_t eb_bits[kMaxFields];
+    uint32_t F;
 };
 
 struct DecodeArgs {
@@ -187,5 +191,54 @@ hipError_t launch_bound_check(const float* const* orig, const float* const* reco
                               hipStream_t s);
 hipError_t launch_field_range(const float* const* x, uint64_t n, uint32_t F, int* keys,
                               hipStream_t s);
+
+// ------------------------------------------------------------ batched form
+// Many snapshots in one launch per stage.  Job tables live in device memory;
+// block g of the flattened list belongs to the job j with
+// prefix[j] <= g < prefix[j+1] (found by a uniform binary search).
+
+__device__ __forceinline__ uint32_t find_job(const uint32_t* __restrict__ prefix, uint32_t njobs,
+                                             uint32_t g) {
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Launch descriptor of a batch, kept in device memory so that a captured
+// graph stays valid when the job table is rebound (counts change, pointers
+// and launch shapes do not).
+struct BatchLaunch {
+    uint32_t njobs;
+    uint32_t total_full;    // full blocks over all jobs
+    uint32_t total_blocks;  // all blocks over all jobs
+    uint32_t ntail;         // jobs whose last block is partial
+    uint32_t tile;          // consecutive blocks taken per work-queue grab
+    const uint32_t* full_prefix;   // njobs + 1
+    const uint32_t* block_prefix;  // njobs + 1
+    const uint32_t* tail_jobs;     // ntail job indices
+    uint32_t* counter;             // [0] encode queue head, [1] decode queue head
+};
+
+// Launch shapes of the batched kernels (fixed for the life of a batch).
+struct BatchShape {
+    uint32_t B;
+    uint32_t grid;        // persistent encode / decode workgroups (one wave each)
+    uint32_t scan_grid;   // workgroups striding over jobs for the scans
+    uint32_t copy_grid;   // 4-wave workgroups striding over blocks for the copies
+    uint32_t tail_grid;   // workgroups striding over the partial tail blocks
+};
+
+hipError_t launch_encode_batch(const EncodeArgs* jobs, const BatchLaunch* L, const BatchShape& S,
+                               hipStream_t s);
+hipError_t launch_scan_batch(const ScanArgs* jobs, const BatchLaunch* L, const BatchShape& S,
+                             hipStream_t s);
+hipError_t launch_copy_batch(const CopyArgs* jobs, const BatchLaunch* L, const BatchShape& S,
+                             hipStream_t s);
+hipError_t launch_decode_batch(const DecodeArgs* jobs, const BatchLaunch* L,
+                               const BatchShape& S, hipStream_t s);
 
 }  // namespace gpz

@@ -214,3 +214,38 @@ def make(kind: str, n: int, seed: int) -> List[np.ndarray]:
     if kind == "lidar":
         return lidar(n, seed)
     raise ValueError(kind)
+
+
+def clusters_device(n: int, seed: int, n_clusters: int = 64, sigma: float = 0.01,
+                    background: float = 0.2, extra_fields: int = 0, device="cuda"):
+    """`clusters` drawn on the GPU with torch's seeded generator (same
+    distribution, different random stream); for large benchmark batches whose
+    host generation would dominate.  Returns float32 CUDA tensors."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    centres = torch.rand((n_clusters, 3), generator=g, dtype=torch.float64, device=device)
+    lab = torch.randint(0, n_clusters, (n,), generator=g, device=device)
+    bg = torch.rand(n, generator=g, dtype=torch.float64, device=device) < background
+    p = centres[lab] + sigma * torch.randn((n, 3), generator=g, dtype=torch.float64, device=device)
+    u = torch.rand((n, 3), generator=g, dtype=torch.float64, device=device)
+    p = torch.where(bg[:, None], u, p)
+    p = torch.remainder(p, 1.0).to(torch.float32)
+    p = torch.where(p >= 1.0, torch.zeros_like(p), p)
+    out = [p[:, a].contiguous() for a in range(3)]
+    for _ in range(extra_fields):
+        out.append(torch.randn(n, generator=g, dtype=torch.float32, device=device))
+    return out
+
+
+def batch_specs(count: int = 256, seed: int = 4, n_min: int = 10_000, n_max: int = 8_000_000):
+    """Shapes of the batched-form snapshots (see batch_snapshots): list of
+    dicts with n, fields, clusters, eb, seed."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    ns = np.maximum(1, np.floor(np.exp(r.uniform(np.log(n_min), np.log(n_max), count)))).astype(np.int64)
+    Fs = r.integers(3, 7, count)
+    ks = r.integers(8, 1025, count)
+    ebs = np.exp(r.uniform(np.log(1e-5), np.log(1e-2), count)).astype(np.float32)
+    seeds = r.integers(0, 2 ** 31, count)
+    return [dict(n=int(ns[i]), fields=int(Fs[i]), clusters=int(ks[i]), eb=float(ebs[i]),
+                 seed=int(seeds[i])) for i in range(count)]

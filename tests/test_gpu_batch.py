@@ -1,0 +1,169 @@
+"""Batched form: every job of a batch must produce exactly the stream (and
+decompressed floats) of the plain per-snapshot path, with or without graph
+capture, on every graph replay, and after rebinding to new jobs."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gpz():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_10305_amd as g
+    g.lib()
+    return g
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_jobs(seed, sizes, fields_per_job=None):
+    from paper_2508_10305_amd import synth
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for i, n in enumerate(sizes):
+        F = fields_per_job[i] if fields_per_job else int(rng.integers(3, 7))
+        host = synth.clusters(n, seed=seed * 1000 + i, n_clusters=int(rng.integers(8, 1025)),
+                              extra_fields=F - 3) if n else [np.zeros(0, np.float32)] * F
+        eb = float(np.exp(rng.uniform(np.log(1e-5), np.log(1e-2))))
+        jobs.append((host, eb))
+    return jobs
+
+
+def plain_results(gpz, jobs):
+    ref = []
+    for host, eb in jobs:
+        n = host[0].size
+        dev = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in host]
+        s, _ = gpz.compress(dev, eb)
+        out = gpz.decompress(s, n, len(host))
+        ref.append((s.cpu().numpy(), [o.cpu().numpy() for o in out]))
+    return ref
+
+
+def build_batch(gpz, jobs, config=None, **kw):
+    from paper_2508_10305_amd.batch import Batch
+    fields, outs, decs, ebs = [], [], [], []
+    for host, eb in jobs:
+        n, F = host[0].size, len(host)
+        fields.append([torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in host])
+        outs.append(torch.zeros(gpz.max_compressed_bytes(n, F), dtype=torch.uint8, device="cuda"))
+        decs.append([torch.full((max(n, 1),), np.nan, dtype=torch.float32, device="cuda")[:n]
+                     for _ in range(F)])
+        ebs.append(eb)
+    b = Batch(fields, ebs, outs, dec=decs, config=config, **kw)
+    return b, fields, outs, decs, ebs
+
+
+def check_batch(b, outs, decs, ref, label):
+    sizes = b.sizes()
+    assert (b.errors() == 0).all(), label
+    for j, (rs, rout) in enumerate(ref):
+        assert int(sizes[j]) == rs.size, f"{label}: job {j} size"
+        got = outs[j][: rs.size].cpu().numpy()
+        assert (got == rs).all(), f"{label}: job {j} stream bytes differ"
+        for f, ro in enumerate(rout):
+            d = decs[j][f].cpu().numpy()
+            assert (d.view(np.uint32) == ro.view(np.uint32)).all(), f"{label}: job {j} field {f}"
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+@pytest.mark.parametrize("tile", [1, 3])
+def test_batch_equals_plain(gpz, use_graph, tile):
+    from paper_2508_10305_amd.batch import default_config
+    sizes = [1, 1023, 1024, 1025, 5000, 0, 70_000, 200_001, 64 * 1024 + 7, 3]
+    jobs = make_jobs(7, sizes)
+    ref = plain_results(gpz, jobs)
+    cfg = default_config()
+    cfg.use_graph = use_graph
+    cfg.tile = tile
+    cfg.grid = 97  # odd persistent grid: blocks are shared unevenly between waves
+    say(f"[case] batch graph={use_graph} tile={tile}")
+    b, fields, outs, decs, ebs = build_batch(gpz, jobs, cfg)
+    b.compress()
+    b.decompress()
+    check_batch(b, outs, decs, ref, f"graph={use_graph} tile={tile}")
+    b.close()
+
+
+def test_batch_matches_oracle(gpz, orc):
+    jobs = make_jobs(11, [3000, 10_000, 1024 * 5], fields_per_job=[3, 5, 6])
+    b, fields, outs, decs, ebs = build_batch(gpz, jobs)
+    b.compress()
+    sizes = b.sizes()
+    for j, (host, eb) in enumerate(jobs):
+        ref, _ = orc.compress(host, eb)
+        assert (outs[j][: int(sizes[j])].cpu().numpy() == ref).all()
+    b.close()
+
+
+def test_graph_replays_with_eager_work_between(gpz):
+    jobs = make_jobs(13, [50_000, 8_000, 120_000])
+    ref = plain_results(gpz, jobs)
+    b, fields, outs, decs, ebs = build_batch(gpz, jobs)
+    for rep in range(4):
+        for o in outs:
+            o.zero_()
+        for d in decs:
+            for t in d:
+                t.fill_(float("nan"))
+        say(f"[case] graph replay {rep}")
+        b.compress()
+        # eager work of the program between replays
+        x = torch.randn(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        _ = (x * 2).sum().item()
+        gpz.compress([t for t in fields[1]], ebs[1])
+        b.decompress()
+        check_batch(b, outs, decs, ref, f"replay {rep}")
+    b.close()
+
+
+def test_rebind_keeps_graphs_valid(gpz):
+    jobs_a = make_jobs(17, [30_000, 2_000, 9_000])
+    jobs_b = make_jobs(19, [100_000, 1_500])
+    ref_b = plain_results(gpz, jobs_b)
+    total_blocks = sum((h[0].size + 1023) // 1024 for h, _ in jobs_a + jobs_b)
+    b, *_ = build_batch(gpz, jobs_a, max_jobs=8, max_blocks=total_blocks)
+    b.compress()
+    b.decompress()
+    torch.cuda.synchronize()
+    # new jobs, same batch object and captured graphs
+    fields, outs, decs, ebs = [], [], [], []
+    for host, eb in jobs_b:
+        n, F = host[0].size, len(host)
+        fields.append([torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in host])
+        outs.append(torch.zeros(gpz.max_compressed_bytes(n, F), dtype=torch.uint8, device="cuda"))
+        decs.append([torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(F)])
+        ebs.append(eb)
+    ws = torch.empty(b.workspace_bytes(fields, ebs, outs, decs), dtype=torch.uint8, device="cuda")
+    say("[case] rebind")
+    b.rebind(fields, ebs, outs, dec=decs, workspace=ws)
+    b.compress()
+    b.decompress()
+    check_batch(b, outs, decs, ref_b, "rebind")
+    b.close()
+
+
+def test_batch_reports_corrupt_stream(gpz):
+    jobs = make_jobs(23, [20_000, 20_000])
+    b, fields, outs, decs, ebs = build_batch(gpz, jobs)
+    b.compress()
+    sizes = b.sizes()
+    # corrupt a record length of job 1 only
+    w = outs[1].view(torch.int32)
+    nb = (20_000 + 1023) // 1024
+    lt = 8 + 2 + len(fields[1])
+    w[lt + 3] += 1
+    b.decompress()
+    err = b.errors()
+    assert err[0] == 0 and err[1] != 0
+    b.close()
