@@ -42,6 +42,9 @@ def main():
     ap.add_argument("--form", choices=["plain", "batched", "serving"], default="plain",
                     help="plain per-snapshot launch (default), batched snapshots, or serving loop")
     ap.add_argument("--jobs", type=int, default=256, help="snapshots of the batched form")
+    ap.add_argument("--requests", type=int, default=20_000, help="requests of the serving form")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="scales the serving request sizes (1.0: 100K-32M particles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the compressor is single-GPU (blocks are independent; "
@@ -51,8 +54,8 @@ def main():
     if args.form == "batched":
         return bench_batched(args)
     if args.form == "serving":
-        import serve_bench
-        return serve_bench.main(args)
+        from paper_2508_10305_amd import serve
+        return serve.bench_main(args, log=log)
 
     import torch
 

@@ -163,7 +163,9 @@ typedef struct {
     const float *eb;            /* host array of F absolute bounds (as for gpz_compress) */
     void *out;                  /* device stream buffer: written by compression, read by
                                    decompression */
-    uint64_t out_capacity;      /* bytes; must be >= gpz_max_compressed_bytes(n, F, p) */
+    uint64_t out_capacity;      /* bytes; >= gpz_max_compressed_bytes(n, F, p) for a job
+                                   that compresses; any upper bound of the stream size for
+                                   a job that only decompresses */
     float *const *dec_fields;   /* host array of F device pointers: decompression output
                                    (NULL for a job that is only compressed) */
 } gpz_job;
@@ -181,8 +183,10 @@ typedef struct gpz_batch gpz_batch;
 /* Fills *c with the defaults (queries the current device's CU count). */
 void gpz_default_batch_config(gpz_batch_config *c);
 
-/* Device workspace for a job list (record slots of every block); 0 on
- * invalid jobs.  All jobs share the parameters p (NULL = defaults). */
+/* Device workspace for a job list (record slots of every block of the jobs
+ * that compress); 0 on invalid jobs.  All jobs share the parameters p
+ * (NULL = defaults).  A batch may be created with no jobs (njobs = 0) and
+ * capacities in cfg, then bound with gpz_batch_rebind. */
 uint64_t gpz_batch_workspace_bytes(const gpz_job *jobs, uint32_t njobs, const gpz_params *p);
 
 /* Creates a batch bound to `jobs` and the caller's workspace d_ws (device,

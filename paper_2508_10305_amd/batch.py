@@ -26,6 +26,7 @@ class _JobArrays:
     """Keeps the host pointer arrays of a job list alive for the C call."""
 
     def __init__(self, fields, ebs, outs, decs):
+        outs = outs or []
         self.njobs = len(outs)
         self.jobs = (Job * max(1, self.njobs))()
         self.keep = []
@@ -70,7 +71,7 @@ class Batch:
         if need == 0:
             raise ValueError("invalid job list")
         if workspace is None:
-            workspace = torch.empty(need, dtype=torch.uint8, device=outs[0].device)
+            workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
         self.ws = workspace
         self.handle = ctypes.c_void_p()
         rc = _lib().gpz_batch_create(ctypes.byref(self.handle), arrays.jobs, arrays.njobs,
@@ -79,6 +80,15 @@ class Batch:
         _check(rc, "gpz_batch_create")
         self.njobs = arrays.njobs
         self._arrays = arrays
+
+    @classmethod
+    def empty(cls, max_jobs: int, max_blocks: int, p: Optional[Params] = None,
+              config: Optional[BatchConfig] = None):
+        """A batch with no jobs yet (bind them with rebind)."""
+        import torch
+        ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+        return cls(None, [], [], dec=None, p=p, config=config, workspace=ws, max_jobs=max_jobs,
+                   max_blocks=max_blocks)
 
     @staticmethod
     def workspace_bytes(fields, ebs, outs, dec=None, p=None) -> int:
@@ -141,7 +151,7 @@ class _DeviceArray:
 
     def __init__(self, ptr: int, n: int, typestr: str):
         self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr,
-                                         "data": (ptr, True), "version": 3, "strides": None}
+                                         "data": (ptr, False), "version": 3, "strides": None}
 
 
 def device_view(ptr: int, n: int, typestr: str):

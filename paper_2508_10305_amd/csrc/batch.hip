@@ -88,15 +88,23 @@ int validate_jobs(const gpz_job* jobs, uint32_t njobs, const gpz_params& p) {
         const uint64_t nb = nblocks_of(J.n, p.block_size);
         const uint64_t maxb =
             4 * (prefix_words(J.n, J.nfields, p.block_size) + nb + (uint64_t)J.nfields * J.n);
-        if (J.out_capacity < maxb) return GPZ_EINVAL;  // a batch never runs out of space
+        // a compressing batch never runs out of space; a stream to decompress
+        // only has to hold its header
+        if (J.fields && J.out_capacity < maxb) return GPZ_EINVAL;
+        if (J.out_capacity < 4 * prefix_words(J.n, J.nfields, p.block_size)) return GPZ_EINVAL;
     }
     return GPZ_OK;
 }
 
+// Record slots of the jobs that compress (decompression needs none).
+uint64_t job_workspace(const gpz_job& J, uint32_t B) {
+    if (!J.fields) return 0;
+    return align256(nblocks_of(J.n, B) * (uint64_t)slot_words_of(J.nfields, B) * 4);
+}
+
 uint64_t jobs_workspace(const gpz_job* jobs, uint32_t njobs, uint32_t B) {
     uint64_t total = 0;
-    for (uint32_t j = 0; j < njobs; j++)
-        total += align256(nblocks_of(jobs[j].n, B) * (uint64_t)slot_words_of(jobs[j].nfields, B) * 4);
+    for (uint32_t j = 0; j < njobs; j++) total += job_workspace(jobs[j], B);
     return total;
 }
 
@@ -145,7 +153,8 @@ int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t
         nsuper_all += nsuper_of(nb);
     }
     if (nblocks_all > b->max_blocks || nsuper_all > b->max_super) return GPZ_EINVAL;
-    if (jobs_workspace(jobs, njobs, B) > ws_bytes || (njobs && !d_ws)) return GPZ_EINVAL;
+    const uint64_t ws_need = jobs_workspace(jobs, njobs, B);
+    if (ws_need > ws_bytes || (ws_need && !d_ws)) return GPZ_EINVAL;
 
     std::vector<EncodeArgs> enc(njobs);
     std::vector<ScanArgs> scan(njobs);
@@ -165,8 +174,8 @@ int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t
         if (J.n % B) tails.push_back(j);
         if (J.n > 0 && !J.fields) can_c = false;
         if (J.n > 0 && !J.dec_fields) can_d = false;
-        uint32_t* temp = reinterpret_cast<uint32_t*>(ws + ws_at);
-        ws_at += align256(nb * (uint64_t)sw * 4);
+        uint32_t* temp = J.fields ? reinterpret_cast<uint32_t*>(ws + ws_at) : nullptr;
+        ws_at += job_workspace(J, B);
         EncodeArgs& e = enc[j];
         ScanArgs& sa = scan[j];
         CopyArgs& ca = copy[j];

@@ -1,0 +1,439 @@
+"""Serving form: a request loop with continuous batching.
+
+Requests to compress or decompress particle sets of different sizes arrive
+over time.  The scheduler admits a request as soon as its device buffers fit
+the HBM budget (an arena allocated once; nothing is allocated per request),
+groups the admitted requests into batches that run on one of several HIP
+streams while earlier batches are still on the GPU, and records each
+request's latency from arrival to observed completion.  The same arrival
+stream can also be served launch-per-request (one plain launch per request)
+for comparison.
+
+Inputs are slices of device-resident pools; decompression requests read
+streams compressed at start-up.  Every result is the same as the request
+processed alone (checked by the tests).
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import Params, _check, _lib, _ptr_array, _stream_handle, max_compressed_bytes, params
+
+ALIGN = 256
+
+
+def _up(x: int) -> int:
+    return (x + ALIGN - 1) // ALIGN * ALIGN
+
+
+def _slot_words(F: int, B: int) -> int:
+    return (1 + F * B + 3) & ~3
+
+
+def compress_ws_bytes(n: int, F: int, B: int) -> int:
+    """Record-slot workspace of one job inside a batch (see the C ABI)."""
+    return _up(((n + B - 1) // B) * _slot_words(F, B) * 4)
+
+
+class Arena:
+    """First-fit allocator over one device buffer: the HBM budget ledger."""
+
+    def __init__(self, nbytes: int, device="cuda"):
+        import torch
+        self.size = _up(nbytes)
+        self.buf = torch.empty(self.size, dtype=torch.uint8, device=device)
+        self.free: List[Tuple[int, int]] = [(0, self.size)]
+        self.used = 0
+        self.peak = 0
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        nbytes = _up(max(nbytes, 1))
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= nbytes:
+                if ln == nbytes:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + nbytes, ln - nbytes)
+                self.used += nbytes
+                self.peak = max(self.peak, self.used)
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int):
+        nbytes = _up(max(nbytes, 1))
+        self.used -= nbytes
+        self.free.append((off, nbytes))
+        self.free.sort()
+        merged = []
+        for o, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free = merged
+
+    def view(self, off: int, nbytes: int, dtype=None):
+        import torch
+        t = self.buf[off: off + nbytes]
+        return t if dtype is None or dtype == torch.uint8 else t.view(dtype)
+
+
+@dataclass
+class Request:
+    rid: int
+    t: float                 # arrival time (s, from the start of the run)
+    op: str                  # "compress" | "decompress"
+    kind: str
+    n: int
+    F: int
+    eb: np.ndarray
+    fields: Sequence = ()    # compress: input views; decompress: none
+    stream: object = None    # decompress: input stream (uint8 view)
+    # filled by the server
+    out_off: int = -1
+    out_bytes: int = 0
+    out: object = None       # compress: stream buffer; decompress: list of field views
+    t_admit: float = 0.0
+    t_done: float = 0.0
+    batch: int = -1
+
+
+@dataclass
+class _Slot:
+    stream: object
+    batch_c: object = None
+    batch_d: object = None
+    ws_off: int = -1
+    ws_bytes: int = 0
+    busy: bool = False
+    event: object = None
+    reqs: list = field(default_factory=list)
+    sizes: object = None
+    err: object = None
+
+
+class Server:
+    """Continuous-batching scheduler over `nstreams` HIP streams."""
+
+    def __init__(self, budget_bytes: int, nstreams: int = 3, max_jobs: int = 64,
+                 max_blocks: int = 1 << 20, p: Optional[Params] = None, config=None,
+                 device="cuda"):
+        import torch
+        self.p = p if p is not None else params(3)
+        self.B = self.p.block_size
+        self.arena = Arena(budget_bytes, device)
+        self.nstreams = nstreams
+        self.max_jobs = max_jobs
+        self.max_blocks = max_blocks
+        self.config = config
+        from .batch import Batch, default_config
+        cfg = config if config is not None else default_config()
+        self.slots = []
+        for _ in range(nstreams):
+            sl = _Slot(stream=torch.cuda.Stream())
+            # batches, graphs and scratch are created once; runs only rebind
+            sl.batch_c = Batch.empty(max_jobs, max_blocks, self.p, cfg)
+            sl.batch_d = Batch.empty(max_jobs, max_blocks, self.p, cfg)
+            sl.batch_c.compress(stream=sl.stream)
+            sl.batch_d.decompress(stream=sl.stream)
+            sl.sizes = torch.zeros(1, dtype=torch.int64, device=device)
+            sl.err = torch.zeros(1, dtype=torch.int32, device=device)
+            self.slots.append(sl)
+        torch.cuda.synchronize()
+        self.batches = 0
+        self.batch_sizes: List[int] = []
+
+    # ------------------------------------------------------------ sizes
+    def _request_bytes(self, r: Request) -> int:
+        if r.op == "compress":
+            return _up(max_compressed_bytes(r.n, r.F, self.p))
+        return sum(_up(4 * r.n) for _ in range(r.F))
+
+    def _admit(self, r: Request, now: float) -> bool:
+        import torch
+        nbytes = self._request_bytes(r)
+        off = self.arena.alloc(nbytes)
+        if off is None:
+            return False
+        r.out_off, r.out_bytes, r.t_admit = off, nbytes, now
+        if r.op == "compress":
+            r.out = self.arena.view(off, nbytes)
+        else:
+            r.out = [self.arena.view(off + f * _up(4 * r.n), 4 * r.n, torch.float32)
+                     for f in range(r.F)]
+        return True
+
+    def _release(self, r: Request):
+        self.arena.release(r.out_off, r.out_bytes)
+
+    # ------------------------------------------------------------ batched launch
+    def _launch(self, slot: _Slot, reqs: List[Request]) -> bool:
+        """Launch the admitted requests `reqs` as one batch per operation."""
+        import torch
+        comp = [r for r in reqs if r.op == "compress"]
+        dec = [r for r in reqs if r.op == "decompress"]
+        ws_need = sum(compress_ws_bytes(r.n, r.F, self.B) for r in comp)
+        ws_off = self.arena.alloc(ws_need) if ws_need else None
+        if ws_need and ws_off is None:
+            return False
+        ws = self.arena.view(ws_off, _up(ws_need)) if ws_need else self.arena.view(0, ALIGN)
+        slot.ws_off, slot.ws_bytes = (ws_off if ws_need else -1), ws_need
+        with torch.cuda.stream(slot.stream):
+            if comp:
+                slot.batch_c.rebind([r.fields for r in comp], [r.eb for r in comp],
+                                    [r.out for r in comp], workspace=ws, stream=slot.stream)
+                slot.batch_c.compress(stream=slot.stream)
+            if dec:
+                slot.batch_d.rebind(None, [r.eb for r in dec], [r.stream for r in dec],
+                                    dec=[r.out for r in dec], workspace=ws, stream=slot.stream)
+                slot.batch_d.decompress(stream=slot.stream)
+            slot.event = torch.cuda.Event()
+            slot.event.record(slot.stream)
+        slot.busy = True
+        slot.reqs = reqs
+        for r in reqs:
+            r.batch = self.batches
+        self.batches += 1
+        self.batch_sizes.append(len(reqs))
+        return True
+
+    # ------------------------------------------------------------ per-request launch
+    def _launch_single(self, slot: _Slot, r: Request) -> bool:
+        import torch
+        s = _stream_handle(slot.stream)
+        if r.op == "compress":
+            ws_need = _up(int(_lib().gpz_compress_workspace_bytes(r.n, r.F, ctypes.byref(self.p))))
+            ws_off = self.arena.alloc(ws_need)
+            if ws_off is None:
+                return False
+            slot.ws_off, slot.ws_bytes = ws_off, ws_need
+            ebs = np.ascontiguousarray(r.eb, np.float32)
+            ptrs = _ptr_array(r.fields)
+            rc = _lib().gpz_compress_async(
+                ctypes.cast(ptrs, ctypes.c_void_p), r.n, r.F, ebs.ctypes.data_as(ctypes.c_void_p),
+                ctypes.byref(self.p), r.out.data_ptr(), r.out.numel(), slot.sizes.data_ptr(), None,
+                self.arena.view(ws_off, ws_need).data_ptr(), ws_need, s)
+            _check(rc, "gpz_compress_async")
+        else:
+            slot.ws_off, slot.ws_bytes = -1, 0
+            ptrs = _ptr_array(r.out)
+            rc = _lib().gpz_decompress_async(r.stream.data_ptr(), r.stream.numel(),
+                                             ctypes.cast(ptrs, ctypes.c_void_p), r.n, r.F,
+                                             ctypes.byref(self.p), slot.err.data_ptr(), s)
+            _check(rc, "gpz_decompress_async")
+        ev = torch.cuda.Event()
+        ev.record(slot.stream)
+        slot.event = ev
+        slot.busy = True
+        slot.reqs = [r]
+        r.batch = self.batches
+        self.batches += 1
+        self.batch_sizes.append(1)
+        return True
+
+    # ------------------------------------------------------------ loop
+    def run(self, requests: List[Request], mode: str = "batched", time_scale: float = 1.0,
+            max_batch: Optional[int] = None, on_done=None) -> Dict:
+        """Serve `requests` (sorted by arrival).  mode: "batched" (continuous
+        batching) or "per_request".  `on_done(request)` is called when a
+        request's result is complete, before its buffers are released.
+        Returns latency and throughput stats."""
+        import torch
+        torch.cuda.synchronize()
+        max_batch = max_batch or self.max_jobs
+        pending = list(requests)
+        waiting: List[Request] = []
+        admitted: List[Request] = []
+        done: List[Request] = []
+        t0 = time.perf_counter()
+        i = 0
+        while len(done) < len(requests):
+            now = time.perf_counter() - t0
+            # completions
+            for slot in self.slots:
+                if slot.busy and slot.event.query():
+                    for r in slot.reqs:
+                        r.t_done = now
+                        if on_done is not None:
+                            on_done(r)
+                        self._release(r)
+                        done.append(r)
+                    if slot.ws_off >= 0:
+                        self.arena.release(slot.ws_off, slot.ws_bytes)
+                    slot.busy, slot.reqs, slot.ws_off = False, [], -1
+            # arrivals
+            while i < len(pending) and pending[i].t * time_scale <= now:
+                waiting.append(pending[i])
+                i += 1
+            # admission by the HBM budget, in arrival order
+            while waiting and self._admit(waiting[0], now):
+                admitted.append(waiting.pop(0))
+            # launch on free streams
+            for slot in self.slots:
+                if not admitted:
+                    break
+                if slot.busy:
+                    continue
+                if mode == "per_request":
+                    r = admitted[0]
+                    if self._launch_single(slot, r):
+                        admitted.pop(0)
+                else:
+                    take, blocks = [], 0
+                    for r in admitted:
+                        nb = (r.n + self.B - 1) // self.B
+                        if len(take) >= max_batch or blocks + nb > self.max_blocks:
+                            break
+                        take.append(r)
+                        blocks += nb
+                    if take and self._launch(slot, take):
+                        del admitted[: len(take)]
+        wall = time.perf_counter() - t0
+        lat = np.array([r.t_done - r.t * time_scale for r in done]) * 1e3
+        nbytes = sum(4 * r.n * r.F for r in done)
+        first = min(r.t for r in requests) * time_scale
+        return {
+            "mode": mode,
+            "requests": len(done),
+            "batches": self.batches,
+            "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()),
+            "wall_s": wall,
+            "sustained_GBps": nbytes / max(1e-9, wall - first) / 1e9,
+            "bytes": nbytes,
+            "arena_peak_bytes": self.arena.peak,
+        }
+
+    def close(self):
+        for s in self.slots:
+            for b in (s.batch_c, s.batch_d):
+                if b is not None:
+                    b.close()
+
+
+# ---------------------------------------------------------------- workload
+
+RELS = (1e-2, 1e-3, 1e-4)
+
+
+def build_pools(max_n: int, seed: int = 5, kinds=("clusters", "cosmology", "md", "lidar"),
+                log=None):
+    """Device-resident input pools, one per generator kind, with the absolute
+    bounds of each relative bound (relative to the pool's field ranges)."""
+    import torch
+
+    from . import rel_ebs, synth
+    pools = {}
+    for ki, kind in enumerate(kinds):
+        t0 = time.time()
+        if kind == "clusters":
+            fields = synth.clusters_device(max_n, seed + ki)
+        else:
+            fields = [torch.from_numpy(f).cuda() for f in synth.make(kind, max_n, seed + ki)]
+        torch.cuda.synchronize()
+        pools[kind] = dict(fields=fields, F=len(fields),
+                           ebs={rel: rel_ebs(fields, rel) for rel in RELS})
+        if log:
+            log(f"[serve] pool {kind}: {max_n} x {len(fields)} in {time.time() - t0:.1f}s")
+    return pools
+
+
+def template_sizes(n_min: int, n_max: int, count: int = 8) -> List[int]:
+    return sorted(set(int(round(x)) for x in np.exp(np.linspace(np.log(n_min), np.log(n_max),
+                                                               count))))
+
+
+def build_templates(pools, sizes: Sequence[int], p: Optional[Params] = None):
+    """Streams compressed at start-up, read by the decompression requests:
+    one per (kind, relative bound, size)."""
+    from . import Compressor
+    out = {}
+    for kind, pool in pools.items():
+        for rel in RELS:
+            for n in sizes:
+                c = Compressor(n, pool["F"], p)
+                s, _ = c.compress([f[:n] for f in pool["fields"]], pool["ebs"][rel])
+                out[(kind, rel, n)] = s.clone()
+    return out
+
+
+def make_requests(pools, templates, sizes, count: int, seed: int, rate: float, n_min: int,
+                  n_max: int) -> List[Request]:
+    from . import synth
+    spec = synth.request_stream(count, seed, rate, n_min, n_max)
+    rng = np.random.default_rng(seed + 1)
+    reqs = []
+    for i, r in enumerate(spec):
+        pool = pools[r["kind"]]
+        if r["op"] == "compress":
+            n = min(r["n"], pool["fields"][0].numel())
+            off = int(rng.integers(0, pool["fields"][0].numel() - n + 1))
+            reqs.append(Request(i, r["t"], "compress", r["kind"], n, pool["F"],
+                                pool["ebs"][r["rel"]],
+                                fields=[f[off: off + n] for f in pool["fields"]]))
+        else:
+            n = min(sizes, key=lambda s: abs(np.log(s) - np.log(r["n"])))
+            reqs.append(Request(i, r["t"], "decompress", r["kind"], n, pool["F"],
+                                pool["ebs"][r["rel"]], stream=templates[(r["kind"], r["rel"], n)]))
+    return reqs
+
+
+def fresh(reqs: List[Request]) -> List[Request]:
+    return [Request(r.rid, r.t, r.op, r.kind, r.n, r.F, r.eb, fields=r.fields, stream=r.stream)
+            for r in reqs]
+
+
+def bench_main(args, log=print):
+    """Serving benchmark: the same Poisson arrival stream served with
+    continuous batching and launch-per-request, at the nominal rate and in
+    overload (a smaller HBM budget, so admission queues)."""
+    import json
+
+    import torch
+    scale = getattr(args, "serve_scale", 1.0)
+    count = getattr(args, "requests", 20_000)
+    n_min, n_max = int(100_000 * scale), int(32_000_000 * scale)
+    pools = build_pools(n_max, log=log)
+    sizes = template_sizes(n_min, n_max)
+    templates = build_templates(pools, sizes)
+    torch.cuda.synchronize()
+    reqs = make_requests(pools, templates, sizes, count, 5, 2000.0, n_min, n_max)
+    results = {}
+    for label, budget, mode in (("batched", 200 << 30, "batched"),
+                                ("per_request", 200 << 30, "per_request"),
+                                ("batched_overload", 8 << 30, "batched"),
+                                ("per_request_overload", 8 << 30, "per_request")):
+        budget = min(budget, int(torch.cuda.mem_get_info()[0] * 0.6))
+        srv = Server(budget, nstreams=3, max_jobs=64, max_blocks=1 << 20)
+        rate_scale = 1.0 if "overload" not in label else 0.1  # 10x arrival rate
+        st = srv.run(fresh(reqs), mode=mode, time_scale=rate_scale)
+        st["budget_bytes"] = budget
+        st["arrival_rate_per_s"] = 2000.0 / rate_scale
+        results[label] = st
+        srv.close()
+        log(f"[serve] {label}: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms "
+            f"{st['sustained_GBps']:.1f} GB/s, {st['batches']} launches")
+        torch.cuda.synchronize()
+    rec = {
+        "metric": "serving p50/p99 latency (ms) and sustained GB/s, continuous batching vs "
+                  "launch-per-request",
+        "form": "serving",
+        "value": round(results["batched"]["p99_ms"], 4),
+        "unit": "ms (p99, batched)",
+        "higher_is_better": False,
+        "results": results,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Poisson {count} requests at 2000/s, sizes log-uniform "
+                               f"{n_min}-{n_max}, kinds clusters/cosmology/md/lidar, rel eb "
+                               "1e-2/1e-3/1e-4, 50/50 compress/decompress",
+                   "decompress_template_sizes": sizes},
+    }
+    print(json.dumps(rec), flush=True)

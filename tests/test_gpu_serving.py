@@ -1,0 +1,86 @@
+"""Serving form: continuous batching must give every request exactly the
+result it gets alone, and admission must respect the HBM budget."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_10305_amd as gpz
+    from paper_2508_10305_amd import serve
+    gpz.lib()
+    pools = serve.build_pools(200_000, seed=3)
+    sizes = serve.template_sizes(2_000, 200_000, count=4)
+    templates = serve.build_templates(pools, sizes)
+    reqs = serve.make_requests(pools, templates, sizes, 80, seed=9, rate=40_000.0, n_min=2_000,
+                               n_max=200_000)
+    return gpz, serve, reqs
+
+
+def alone(gpz, r):
+    if r.op == "compress":
+        s, _ = gpz.compress(list(r.fields), r.eb)
+        return s.cpu().numpy()
+    out = gpz.decompress(r.stream, r.n, r.F)
+    return [o.cpu().numpy() for o in out]
+
+
+def snapshot(results):
+    """on_done callback: keep a host copy of each result before its buffer
+    is reused."""
+    def keep(r):
+        if r.op == "compress":
+            results[r.rid] = r.out.cpu().numpy().copy()
+        else:
+            results[r.rid] = [o.cpu().numpy().copy() for o in r.out]
+    return keep
+
+
+def check_same(gpz, reqs, results):
+    for r in reqs:
+        ref = alone(gpz, r)
+        got = results[r.rid]
+        if r.op == "compress":
+            assert (got[: ref.size] == ref).all(), f"request {r.rid}: stream differs in the mix"
+        else:
+            for f in range(r.F):
+                assert (got[f].view(np.uint32) == ref[f].view(np.uint32)).all(), f"request {r.rid}"
+
+
+@pytest.mark.parametrize("mode", ["batched", "per_request"])
+def test_each_result_same_alone_and_in_the_mix(setup, mode):
+    gpz, serve, reqs = setup
+    srv = serve.Server(4 << 30, nstreams=3, max_jobs=16, max_blocks=1 << 14)
+    rs = serve.fresh(reqs)
+    print(f"[case] serving {mode}", flush=True)
+    results = {}
+    st = srv.run(rs, mode=mode, on_done=snapshot(results))
+    torch.cuda.synchronize()
+    check_same(gpz, rs, results)
+    assert st["requests"] == len(reqs)
+    if mode == "batched":
+        assert st["mean_batch"] >= 1.0
+    srv.close()
+
+
+def test_admission_respects_budget_and_queues(setup):
+    gpz, serve, reqs = setup
+    # a budget that holds only a few requests at a time
+    budget = 24 << 20
+    srv = serve.Server(budget, nstreams=2, max_jobs=8, max_blocks=1 << 12)
+    rs = serve.fresh(reqs)
+    print("[case] serving overload", flush=True)
+    st = srv.run(rs, mode="batched")
+    assert st["arena_peak_bytes"] <= srv.arena.size
+    queued = [r for r in rs if r.t_admit > r.t + 1e-4]
+    assert queued, "a small budget must make admission wait"
+    assert st["requests"] == len(reqs)
+    srv.close()
