@@ -39,8 +39,12 @@ def main():
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--cpu-sample-blocks", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["plain", "batched", "serving"], default="plain",
-                    help="plain per-snapshot launch (default), batched snapshots, or serving loop")
+    ap.add_argument("--form", choices=["plain", "batched", "serving", "copy"], default="plain",
+                    help="plain per-snapshot launch (default), batched snapshots, serving loop, "
+                         "or a plain device copy of the snapshot's bytes (HBM reference)")
+    ap.add_argument("--batch-grid", type=int, default=0,
+                    help="batched form: persistent grid (skips the autotuner with --batch-tile)")
+    ap.add_argument("--batch-tile", type=int, default=0)
     ap.add_argument("--jobs", type=int, default=256, help="snapshots of the batched form")
     ap.add_argument("--requests", type=int, default=20_000, help="requests of the serving form")
     ap.add_argument("--serve-scale", type=float, default=1.0,
@@ -56,6 +60,8 @@ def main():
     if args.form == "serving":
         from paper_2508_10305_amd import serve
         return serve.bench_main(args, log=log)
+    if args.form == "copy":
+        return bench_copy(args)
 
     import torch
 
@@ -187,6 +193,30 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
+def bench_copy(args):
+    """A plain device-to-device copy of the snapshot's bytes (6 float32 fields
+    of --n particles): the HBM rate a streaming kernel reaches on this GPU, and
+    the known-size kernel that scales the hardware byte counters."""
+    import torch
+    S = 4 * args.n * 6
+    x = torch.empty(S // 4, dtype=torch.float32, device="cuda").uniform_()
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    print(json.dumps({"metric": "device copy GB/s (read + write)", "form": "copy",
+                      "value": round(2 * S / (ms * 1e-3) / 1e9, 2), "unit": "GB/s",
+                      "ms_per_step": round(ms, 4), "bytes_read": S, "bytes_written": S,
+                      "steps": args.steps}), flush=True)
+
+
 def bench_batched(args):
     """Batched form: snapshots of uneven sizes (log-uniform 10K..8M particles,
     3-6 fields, 8-1024 clusters, abs eb log-uniform 1e-5..1e-2) compressed and
@@ -260,7 +290,10 @@ def bench_batched(args):
 
     total_blocks = sum((sp["n"] + 1023) // 1024 for sp in specs)
     key = autotune.shape_key(torch.cuda.get_device_name(0), 1024, total_blocks, len(specs))
-    tuned = autotune.tune(run, cus, key, use_cache=False, log=log)
+    if args.batch_grid and args.batch_tile:
+        tuned = {"grid": args.batch_grid, "tile": args.batch_tile, "table": []}
+    else:
+        tuned = autotune.tune(run, cus, key, use_cache=False, log=log)
     cfg = default_config()
     cfg.grid, cfg.tile, cfg.use_graph = tuned["grid"], tuned["tile"], 1
     b = Batch(fields, ebs, outs, dec=decs, p=p, config=cfg, workspace=ws)

@@ -168,6 +168,9 @@ typedef struct {
                                    a job that only decompresses */
     float *const *dec_fields;   /* host array of F device pointers: decompression output
                                    (NULL for a job that is only compressed) */
+    void *ws;                   /* device record-slot workspace of this job (at least
+                                   gpz_compress_workspace_bytes(n, F, p) bytes), or NULL to
+                                   carve it from the batch workspace */
 } gpz_job;
 
 typedef struct {
@@ -184,7 +187,7 @@ typedef struct gpz_batch gpz_batch;
 void gpz_default_batch_config(gpz_batch_config *c);
 
 /* Device workspace for a job list (record slots of every block of the jobs
- * that compress); 0 on invalid jobs.  All jobs share the parameters p
+ * that compress without their own `ws`); 0 on invalid jobs.  All jobs share the parameters p
  * (NULL = defaults).  A batch may be created with no jobs (njobs = 0) and
  * capacities in cfg, then bound with gpz_batch_rebind. */
 uint64_t gpz_batch_workspace_bytes(const gpz_job *jobs, uint32_t njobs, const gpz_params *p);

@@ -49,7 +49,8 @@ class Params(ctypes.Structure):
 class Job(ctypes.Structure):
     _fields_ = [("fields", ctypes.c_void_p), ("n", ctypes.c_uint64), ("nfields", ctypes.c_uint32),
                 ("eb", ctypes.c_void_p), ("out", ctypes.c_void_p),
-                ("out_capacity", ctypes.c_uint64), ("dec_fields", ctypes.c_void_p)]
+                ("out_capacity", ctypes.c_uint64), ("dec_fields", ctypes.c_void_p),
+                ("ws", ctypes.c_void_p)]
 
 
 class BatchConfig(ctypes.Structure):

@@ -25,7 +25,7 @@ def default_config() -> BatchConfig:
 class _JobArrays:
     """Keeps the host pointer arrays of a job list alive for the C call."""
 
-    def __init__(self, fields, ebs, outs, decs):
+    def __init__(self, fields, ebs, outs, decs, wss=None):
         outs = outs or []
         self.njobs = len(outs)
         self.jobs = (Job * max(1, self.njobs))()
@@ -47,6 +47,7 @@ class _JobArrays:
             J.out = outs[j].data_ptr()
             J.out_capacity = outs[j].numel()
             J.dec_fields = ctypes.cast(da, ctypes.c_void_p) if da is not None else None
+            J.ws = wss[j].data_ptr() if wss is not None and wss[j] is not None else None
 
 
 class Batch:
@@ -96,8 +97,10 @@ class Batch:
         pp = p if p is not None else params(3)
         return int(_lib().gpz_batch_workspace_bytes(arrays.jobs, arrays.njobs, ctypes.byref(pp)))
 
-    def rebind(self, fields, ebs, outs, dec=None, workspace=None, stream=None):
-        arrays = _JobArrays(fields, ebs, outs, dec)
+    def rebind(self, fields, ebs, outs, dec=None, workspace=None, stream=None, job_ws=None):
+        """Bind new jobs; `job_ws[j]` optionally gives job j its own record-slot
+        workspace (then `workspace` only has to hold the others)."""
+        arrays = _JobArrays(fields, ebs, outs, dec, job_ws)
         ws = workspace if workspace is not None else self.ws
         rc = _lib().gpz_batch_rebind(self.handle, arrays.jobs, arrays.njobs, ws.data_ptr(),
                                      ws.numel(), _stream_handle(stream))

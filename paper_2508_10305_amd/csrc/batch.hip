@@ -96,9 +96,10 @@ int validate_jobs(const gpz_job* jobs, uint32_t njobs, const gpz_params& p) {
     return GPZ_OK;
 }
 
-// Record slots of the jobs that compress (decompression needs none).
+// Record slots the batch workspace must hold for a job: none when the job
+// brings its own or only decompresses.
 uint64_t job_workspace(const gpz_job& J, uint32_t B) {
-    if (!J.fields) return 0;
+    if (!J.fields || J.ws) return 0;
     return align256(nblocks_of(J.n, B) * (uint64_t)slot_words_of(J.nfields, B) * 4);
 }
 
@@ -174,7 +175,9 @@ int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t
         if (J.n % B) tails.push_back(j);
         if (J.n > 0 && !J.fields) can_c = false;
         if (J.n > 0 && !J.dec_fields) can_d = false;
-        uint32_t* temp = J.fields ? reinterpret_cast<uint32_t*>(ws + ws_at) : nullptr;
+        uint32_t* temp = !J.fields ? nullptr
+                         : J.ws   ? static_cast<uint32_t*>(J.ws)
+                                  : reinterpret_cast<uint32_t*>(ws + ws_at);
         ws_at += job_workspace(J, B);
         EncodeArgs& e = enc[j];
         ScanArgs& sa = scan[j];

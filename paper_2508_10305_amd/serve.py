@@ -94,6 +94,7 @@ class Request:
     eb: np.ndarray
     fields: Sequence = ()    # compress: input views; decompress: none
     stream: object = None    # decompress: input stream (uint8 view)
+    ws: object = None        # compress: record-slot workspace (reserved at admission)
     # filled by the server
     out_off: int = -1
     out_bytes: int = 0
@@ -150,9 +151,18 @@ class Server:
 
     # ------------------------------------------------------------ sizes
     def _request_bytes(self, r: Request) -> int:
+        """Everything a request holds while admitted: the stream buffer and
+        record-slot workspace of a compression, the output fields of a
+        decompression."""
         if r.op == "compress":
-            return _up(max_compressed_bytes(r.n, r.F, self.p))
+            return _up(max_compressed_bytes(r.n, r.F, self.p)) + self._ws_bytes(r)
         return sum(_up(4 * r.n) for _ in range(r.F))
+
+    def _ws_bytes(self, r: Request) -> int:
+        # the plain call's workspace (record slots first, then its small
+        # tables) also serves as the job's record slots inside a batch
+        plain = int(_lib().gpz_compress_workspace_bytes(r.n, r.F, ctypes.byref(self.p)))
+        return _up(max(plain, compress_ws_bytes(r.n, r.F, self.B)))
 
     def _admit(self, r: Request, now: float) -> bool:
         import torch
@@ -162,7 +172,9 @@ class Server:
             return False
         r.out_off, r.out_bytes, r.t_admit = off, nbytes, now
         if r.op == "compress":
-            r.out = self.arena.view(off, nbytes)
+            ob = _up(max_compressed_bytes(r.n, r.F, self.p))
+            r.out = self.arena.view(off, ob)
+            r.ws = self.arena.view(off + ob, nbytes - ob)
         else:
             r.out = [self.arena.view(off + f * _up(4 * r.n), 4 * r.n, torch.float32)
                      for f in range(r.F)]
@@ -177,16 +189,13 @@ class Server:
         import torch
         comp = [r for r in reqs if r.op == "compress"]
         dec = [r for r in reqs if r.op == "decompress"]
-        ws_need = sum(compress_ws_bytes(r.n, r.F, self.B) for r in comp)
-        ws_off = self.arena.alloc(ws_need) if ws_need else None
-        if ws_need and ws_off is None:
-            return False
-        ws = self.arena.view(ws_off, _up(ws_need)) if ws_need else self.arena.view(0, ALIGN)
-        slot.ws_off, slot.ws_bytes = (ws_off if ws_need else -1), ws_need
+        ws = self.arena.view(0, ALIGN)  # every job brings its own workspace
+        slot.ws_off, slot.ws_bytes = -1, 0
         with torch.cuda.stream(slot.stream):
             if comp:
                 slot.batch_c.rebind([r.fields for r in comp], [r.eb for r in comp],
-                                    [r.out for r in comp], workspace=ws, stream=slot.stream)
+                                    [r.out for r in comp], workspace=ws, stream=slot.stream,
+                                    job_ws=[r.ws for r in comp])
                 slot.batch_c.compress(stream=slot.stream)
             if dec:
                 slot.batch_d.rebind(None, [r.eb for r in dec], [r.stream for r in dec],
@@ -206,21 +215,16 @@ class Server:
     def _launch_single(self, slot: _Slot, r: Request) -> bool:
         import torch
         s = _stream_handle(slot.stream)
+        slot.ws_off, slot.ws_bytes = -1, 0
         if r.op == "compress":
-            ws_need = _up(int(_lib().gpz_compress_workspace_bytes(r.n, r.F, ctypes.byref(self.p))))
-            ws_off = self.arena.alloc(ws_need)
-            if ws_off is None:
-                return False
-            slot.ws_off, slot.ws_bytes = ws_off, ws_need
             ebs = np.ascontiguousarray(r.eb, np.float32)
             ptrs = _ptr_array(r.fields)
             rc = _lib().gpz_compress_async(
                 ctypes.cast(ptrs, ctypes.c_void_p), r.n, r.F, ebs.ctypes.data_as(ctypes.c_void_p),
                 ctypes.byref(self.p), r.out.data_ptr(), r.out.numel(), slot.sizes.data_ptr(), None,
-                self.arena.view(ws_off, ws_need).data_ptr(), ws_need, s)
+                r.ws.data_ptr(), r.ws.numel(), s)
             _check(rc, "gpz_compress_async")
         else:
-            slot.ws_off, slot.ws_bytes = -1, 0
             ptrs = _ptr_array(r.out)
             rc = _lib().gpz_decompress_async(r.stream.data_ptr(), r.stream.numel(),
                                              ctypes.cast(ptrs, ctypes.c_void_p), r.n, r.F,
@@ -238,7 +242,7 @@ class Server:
 
     # ------------------------------------------------------------ loop
     def run(self, requests: List[Request], mode: str = "batched", time_scale: float = 1.0,
-            max_batch: Optional[int] = None, on_done=None) -> Dict:
+            max_batch: Optional[int] = None, on_done=None, stall_timeout: float = 60.0) -> Dict:
         """Serve `requests` (sorted by arrival).  mode: "batched" (continuous
         batching) or "per_request".  `on_done(request)` is called when a
         request's result is complete, before its buffers are released.
@@ -250,10 +254,14 @@ class Server:
         waiting: List[Request] = []
         admitted: List[Request] = []
         done: List[Request] = []
+        rejected: List[Request] = []
         t0 = time.perf_counter()
+        last_progress = 0.0
         i = 0
-        while len(done) < len(requests):
+        while len(done) + len(rejected) < len(requests):
             now = time.perf_counter() - t0
+            if now - last_progress > stall_timeout:
+                raise RuntimeError("serving loop made no progress")
             # completions
             for slot in self.slots:
                 if slot.busy and slot.event.query():
@@ -263,13 +271,21 @@ class Server:
                             on_done(r)
                         self._release(r)
                         done.append(r)
+                    last_progress = now
                     if slot.ws_off >= 0:
                         self.arena.release(slot.ws_off, slot.ws_bytes)
                     slot.busy, slot.reqs, slot.ws_off = False, [], -1
             # arrivals
             while i < len(pending) and pending[i].t * time_scale <= now:
-                waiting.append(pending[i])
+                r = pending[i]
                 i += 1
+                nb = (r.n + self.B - 1) // self.B
+                if self._request_bytes(r) > self.arena.size or (
+                        mode == "batched" and nb > self.max_blocks):
+                    rejected.append(r)  # can never fit the budget or a batch
+                else:
+                    waiting.append(r)
+                last_progress = now
             # admission by the HBM budget, in arrival order
             while waiting and self._admit(waiting[0], now):
                 admitted.append(waiting.pop(0))
@@ -283,6 +299,7 @@ class Server:
                     r = admitted[0]
                     if self._launch_single(slot, r):
                         admitted.pop(0)
+                        last_progress = now
                 else:
                     take, blocks = [], 0
                     for r in admitted:
@@ -293,6 +310,7 @@ class Server:
                         blocks += nb
                     if take and self._launch(slot, take):
                         del admitted[: len(take)]
+                        last_progress = now
         wall = time.perf_counter() - t0
         lat = np.array([r.t_done - r.t * time_scale for r in done]) * 1e3
         nbytes = sum(4 * r.n * r.F for r in done)
@@ -300,6 +318,7 @@ class Server:
         return {
             "mode": mode,
             "requests": len(done),
+            "rejected": len(rejected),
             "batches": self.batches,
             "mean_batch": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
             "p50_ms": float(np.percentile(lat, 50)),
