@@ -699,7 +699,9 @@ int oracle_decompress(const uint8_t *in, uint64_t bytes, float *const *out, uint
 
 /* recon[f][j] is compared with orig[f][perm[j]] (perm NULL: identity).
  * A pair passes when its bits are identical or |recon - orig| <= eb in
- * IEEE double.  max_err is over pairs whose difference is a number. */
+ * IEEE double.  max_err is over pairs whose difference is a number.  A
+ * permutation entry outside [0, n) names no original value and counts as a
+ * violation. */
 int oracle_bound_check(const float *const *orig, const float *const *recon, const uint32_t *perm,
                        uint64_t n, uint32_t F, const float *eb, uint64_t *violations,
                        double *max_err) {
@@ -707,6 +709,10 @@ int oracle_bound_check(const float *const *orig, const float *const *recon, cons
         uint64_t v = 0;
         double m = 0.0;
         for (uint64_t j = 0; j < n; j++) {
+            if (perm && perm[j] >= n) {  /* no original to compare with */
+                v++;
+                continue;
+            }
             float x = orig[f][perm ? perm[j] : j];
             float y = recon[f][j];
             double d = fabs((double)y - (double)x);

@@ -393,3 +393,19 @@ def test_bound_check_counts_violations(orc):
     v, m = orc.bound_check([x], [y], 1e-3)
     assert v.tolist() == [2]
     assert abs(m[0] - abs(float(y[5]) - float(x[5]))) < 1e-12
+
+
+def test_bound_check_permutation_and_invalid_entries(orc):
+    """A reversal permutation pairs recon[j] with orig[n-1-j]; entries outside
+    [0, n) count as violations without being read."""
+    x = np.arange(8, dtype=np.float32)
+    y = x[::-1].copy()
+    perm = np.arange(8, dtype=np.uint32)[::-1].copy()
+    v, m = orc.bound_check([x], [y], 1e-3, perm=perm)
+    assert v.tolist() == [0] and m.tolist() == [0.0]
+    v, _ = orc.bound_check([x], [x], 1e-3, perm=perm)  # wrong pairing: 8 pairs off by >= 1
+    assert v.tolist() == [8]
+    bad = perm.copy()
+    bad[[0, 3]] = [8, 0xFFFFFFFF]
+    v, m = orc.bound_check([x], [y], 1e-3, perm=bad)
+    assert v.tolist() == [2] and m.tolist() == [0.0]
