@@ -30,6 +30,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_encode_cosmology64M.md")
+ENCODER_SOURCES = ("paper_2508_10305_amd/csrc/encode.hip", "paper_2508_10305_amd/csrc/gpz_internal.h")
+
+
+def encoder_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ENCODER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per encoder launch from the committed counter summary, when
+    it was taken on the encoder source as it is now (else None)."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            kv = dict(line[2:].split(": ", 1) for line in f.read().splitlines()
+                      if line.startswith("- ") and ": " in line)
+        if kv.get("encoder_source_sha256", "").strip() != encoder_source_hash():
+            return None
+        return int(kv["traffic_bytes_per_launch"].strip())
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -37,7 +64,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=64_000_000)
     ap.add_argument("--rel", type=float, default=1e-3)
-    ap.add_argument("--cpu-sample-blocks", type=int, default=1500)
+    ap.add_argument("--cpu-sample-blocks", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", choices=["plain", "batched", "serving", "copy"], default="plain",
                     help="plain per-snapshot launch (default), batched snapshots, serving loop, "
@@ -92,12 +119,12 @@ def main():
     stream, perm = comp.compress(fields, eb, want_perm=True)
     C = int(stream.numel())
     gpz.decompress(stream, n, F, out=outs)
-    viol, maxerr = gpz.bound_check(fields, outs, eb, perm=perm)
+    est = gpz.error_stats(fields, outs, eb, perm=perm)
+    viol, maxerr = est["violations"], est["max_abs_err"]
     assert int(viol.sum()) == 0, f"bound violated: {viol}"
+    outl, raw_blocks = gpz.stream_stats(stream, n, F)
     log(f"[bench] S={S} C={C} CR={S / C:.3f} max_err/eb={(maxerr / eb).max():.4f}")
     nb = (n + p.block_size - 1) // p.block_size
-    prefix_bytes = 4 * (8 + 2 * ((nb + 63) // 64) + F + nb)
-    rec_bytes = C - prefix_bytes
 
     def step():
         comp.compress_async(fields, eb)
@@ -132,18 +159,56 @@ def main():
     assert int(err.item()) == 0, "decoder flagged the stream"
     ms_step = e0.elapsed_time(e1) / args.steps
     avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt.items()}
-    t_c = avg["encode"] + avg["scan"] + avg["copy"]
+    t_c = avg["prepare"] + avg["encode"] + avg["scan"] + avg["copy"]
     t_d = avg["decode"]
     value = 2 * S / (ms_step * 1e-3) / 1e9
 
-    algo = {"encode": S + rec_bytes, "decode": C + S, "copy": 2 * rec_bytes, "scan": 12 * nb}
+    # algorithmic bytes per launch: what each kernel must read and write.  The
+    # encoder reads the snapshot and writes the records (C minus the stream's
+    # tables) to their slots; the copy reads and writes the records once more.
+    rec = C - 4 * (8 + 2 * ((nb + 63) // 64) + F + nb)
+    nsup = (nb + 63) // 64
+    algo = {"encode": S + rec, "decode": C + S, "prepare": 4 * (2 * nb + 4 + nsup),
+            "scan": 12 * nsup, "copy": 2 * rec}
     dominant = max(avg, key=lambda k: avg[k])
     ach = algo[dominant] / (avg[dominant] * 1e-3) / 1e9
+    traffic = None
+    if dominant == "encode" and n == 64_000_000 and F == 6 and args.rel == 1e-3:
+        traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": dominant}
+                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": dominant,
+                "algorithmic_bytes": algo[dominant]}
     kernels = {k: {"ms": round(avg[k], 4),
                    "algorithmic_GBps": round(algo[k] / (avg[k] * 1e-3) / 1e9, 1) if avg[k] else None}
                for k in avg}
+
+    # A/B: single-pass look-back compaction (encoder places its own record)
+    # against the default three launches (encode, scan, copy); same stream
+    p1 = gpz.params(F, single_pass=True)
+    comp1 = gpz.Compressor(n, F, p1, device=dev)
+    s1, _ = comp1.compress(fields, eb)
+    assert torch.equal(s1, stream), "single-pass compaction wrote a different stream"
+    del s1
+    for _ in range(args.warmup):
+        comp1.compress_async(fields, eb)
+    torch.cuda.synchronize()
+    gpz.set_timing(True)
+    gpz.timing_collect()
+    for _ in range(args.steps):
+        comp1.compress_async(fields, eb)
+    torch.cuda.synchronize()
+    gpz.set_timing(False)
+    kt1 = gpz.timing_collect()
+    avg1 = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kt1.items()}
+    t_c1 = avg1["prepare"] + avg1["encode"]
+    del comp1
+    compaction_ab = {
+        "three_step_compress_ms": round(t_c, 4),
+        "three_step_kernels_ms": {k: round(avg[k], 4) for k in ("prepare", "encode", "scan",
+                                                                 "copy")},
+        "single_pass_compress_ms": round(t_c1, 4),
+        "single_pass_kernels_ms": {k: round(avg1[k], 4) for k in ("prepare", "encode")},
+    }
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -185,7 +250,12 @@ def main():
         "decompress_GBps": round(S / (t_d * 1e-3) / 1e9, 2),
         "compression_ratio": round(S / C, 4),
         "max_abs_err_over_eb": round(float((maxerr / eb).max()), 6),
+        "bit_rate_bits_per_value": round(8 * C / (n * F), 4),
+        "aggregate_psnr_db": round(est["psnr"], 3),
+        "outlier_fraction": float(outl.sum()) / (n * F),
+        "raw_blocks": raw_blocks,
         "kernels": kernels,
+        "compaction_ab": compaction_ab,
         "field_range_ms": round(range_ms, 3),
         "plain_latency_ms": {"p50": round(lat[len(lat) // 2], 3),
                              "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3)},

@@ -50,13 +50,22 @@ typedef enum {
  * key_fields : KF, 1..3 and <= F: the first KF fields are the spatial
  *              coordinates whose segment IDs form the sort key.  Default
  *              min(F, 3).
+ * flags      : 0 (default) or GPZ_FLAG_SINGLE_PASS.  Compression only; the
+ *              stream is the same byte for byte either way.
  */
 typedef struct {
     uint32_t block_size;
     uint32_t seg_bits;
     uint32_t key_fields;
-    uint32_t reserved; /* must be 0 */
+    uint32_t flags;
 } gpz_params;
+
+/* Default compaction, the paper's design (Sec. 4.4): records to workspace
+ * slots, a device scan of their lengths, a copy into the stream.  With this
+ * flag the encoder places each record itself after a single-pass look-back
+ * over the lengths of the earlier blocks (one launch fewer, no record copy,
+ * but every block waits for the blocks before it; slower on MI355X). */
+#define GPZ_FLAG_SINGLE_PASS 1u
 
 /* Fills *p with the defaults for F fields. */
 void gpz_default_params(gpz_params *p, uint32_t nfields);
@@ -65,14 +74,17 @@ void gpz_default_params(gpz_params *p, uint32_t nfields);
  * Returns 0 for invalid parameters. */
 uint64_t gpz_max_compressed_bytes(uint64_t n, uint32_t nfields, const gpz_params *p);
 
-/* Device workspace gpz_compress needs (per-block record slots, sizes,
- * offsets): about 4*n*F bytes.  Returns 0 for invalid parameters. */
+/* Device workspace gpz_compress needs (per-block record slots, lengths,
+ * superblock sums and offsets, one look-back word per block): about 4*n*F
+ * bytes.  Returns 0 for invalid parameters. */
 uint64_t gpz_compress_workspace_bytes(uint64_t n, uint32_t nfields, const gpz_params *p);
 
 /* Device workspace gpz_decompress needs (an error flag). */
 uint64_t gpz_decompress_workspace_bytes(void);
 
-/* Compress n particles x F float32 fields (Sec. 4.1-4.4).
+/* Compress n particles x F float32 fields (Sec. 4.1-4.4): a clearing
+ * kernel, the block encoder, the length scan and the record copy
+ * (GPZ_FLAG_SINGLE_PASS: clearing kernel and encoder only).
  *  h_fields     host array of F device pointers, each to n floats.
  *  h_eb         host array of F absolute error bounds (each in [2^-120, 2^120]).
  *  p            parameters (NULL = defaults).
@@ -124,6 +136,26 @@ int gpz_decompress_async(const void *d_in, uint64_t in_bytes, float *const *h_fi
 int gpz_bound_check(const float *const *h_orig, const float *const *h_recon,
                     const uint32_t *d_perm, uint64_t n, uint32_t nfields, const float *h_eb,
                     uint64_t *h_violations, double *h_max_abs_err, void *stream);
+
+/* As gpz_bound_check, and also h_sum_sq_err[F] (nullable): the sum over
+ * pairs whose difference is a number of (recon - orig)^2 in double, from
+ * which the normalized RMSE of every field and the aggregate PSNR of the
+ * rate-distortion analysis (Sec. 2) follow.  The summation order is not
+ * fixed: the sums may differ from a sequential sum in the last bits.
+ * Synchronizes `stream`. */
+int gpz_error_stats(const float *const *h_orig, const float *const *h_recon,
+                    const uint32_t *d_perm, uint64_t n, uint32_t nfields, const float *h_eb,
+                    uint64_t *h_violations, double *h_max_abs_err, double *h_sum_sq_err,
+                    void *stream);
+
+/* Structure statistics of a stream of n particles x F fields in device
+ * memory (in_bytes: at least the stream length): h_outliers[F] receives the
+ * number of values each field stores verbatim in coded blocks (Sec. 4.1
+ * outliers), *h_raw_blocks the number of blocks stored raw.  GPZ_ECORRUPT
+ * on a malformed header or record structure, GPZ_EINVAL when n or F differ
+ * from the header.  Synchronizes `stream`. */
+int gpz_stream_stats(const void *d_in, uint64_t in_bytes, uint64_t n, uint32_t nfields,
+                     uint64_t *h_outliers, uint64_t *h_raw_blocks, void *stream);
 
 /* Per-field minimum and maximum over finite values (h_minmax[2F]: min, max;
  * 0, 0 for a field with none; a zero extreme is returned as +0.0), used to
@@ -222,8 +254,9 @@ int gpz_batch_destroy(gpz_batch *b);
  * While enabled (per host thread), every compress / decompress call records
  * an event pair around each of its kernels.  gpz_timing_collect waits for
  * the recorded events, adds up the durations per kernel kind into
- * total_ms[kind] with launch counts[kind] (kind 0 encode, 1 length scan,
- * 2 record copy, 3 decode; arrays of nkinds entries) and clears the log. */
+ * total_ms[kind] with launch counts[kind] (kind 0 encode, 1 workspace
+ * clearing, 2 decode, 3 length scan, 4 record copy; arrays of nkinds
+ * entries) and clears the log. */
 int gpz_set_timing(int enable);
 int gpz_timing_collect(double *total_ms, uint32_t *counts, int nkinds);
 

@@ -86,6 +86,12 @@ def lib():
                                          u64p, f64p]
         L.oracle_field_range.restype = ctypes.c_int
         L.oracle_field_range.argtypes = [fpp, ctypes.c_uint64, ctypes.c_uint32, f32p]
+        L.oracle_error_stats.restype = ctypes.c_int
+        L.oracle_error_stats.argtypes = [fpp, fpp, u32p, ctypes.c_uint64, ctypes.c_uint32, f64p,
+                                         f64p, f64p]
+        L.oracle_stream_stats.restype = ctypes.c_int
+        L.oracle_stream_stats.argtypes = [u8p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                          u64p, u64p]
         L.oracle_rel_to_abs.restype = ctypes.c_float
         L.oracle_rel_to_abs.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
         _lib = L
@@ -281,3 +287,32 @@ def rel_to_abs(rel: float, lo: float, hi: float) -> float:
 def rel_ebs(fields: Sequence[np.ndarray], rel: float) -> np.ndarray:
     mm = field_range(fields)
     return np.array([rel_to_abs(rel, float(a), float(b)) for a, b in mm], np.float32)
+
+
+def error_stats(orig: Sequence[np.ndarray], recon: Sequence[np.ndarray], perm=None) -> dict:
+    """Per-field sum of squared errors and NRMSE, and the aggregate PSNR (dB)."""
+    orig = [_f32(f) for f in orig]
+    recon = [_f32(f) for f in recon]
+    F = len(orig)
+    n = orig[0].size
+    ss = np.zeros(F, np.float64)
+    nr = np.zeros(F, np.float64)
+    ps = np.zeros(1, np.float64)
+    p = None if perm is None else np.ascontiguousarray(perm, dtype=np.uint32)
+    lib().oracle_error_stats(_field_ptrs(orig), _field_ptrs(recon),
+                             None if p is None else _ptr(p, ctypes.c_uint32), n, F,
+                             _ptr(ss, ctypes.c_double), _ptr(nr, ctypes.c_double),
+                             _ptr(ps, ctypes.c_double))
+    return {"sum_sq": ss, "nrmse": nr, "psnr": float(ps[0])}
+
+
+def stream_stats(stream: np.ndarray, n: int, F: int):
+    """(outliers per field, raw blocks) of a stream."""
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    out = np.zeros(F, np.uint64)
+    raw = np.zeros(1, np.uint64)
+    rc = lib().oracle_stream_stats(_ptr(s, ctypes.c_uint8), s.size, n, F,
+                                   _ptr(out, ctypes.c_uint64), _ptr(raw, ctypes.c_uint64))
+    if rc != OK:
+        raise OracleError(rc, "stream_stats")
+    return out, int(raw[0])

@@ -747,6 +747,78 @@ int oracle_field_range(const float *const *fields, uint64_t n, uint32_t F, float
     return OR_OK;
 }
 
+/* Rate-distortion statistics of a reconstruction (Sec. 2): per field the sum
+ * of squared differences recon[f][j] - orig[f][perm[j]] in double, summed in
+ * position order over the pairs whose difference is a number (perm entries
+ * outside [0, n) are skipped); then the normalized RMSE of every field,
+ * sqrt(sum_sq / n) / (max - min) over the original field's finite values,
+ * and the aggregate PSNR -20 log10 sqrt(mean over fields of NRMSE^2).  A
+ * field with a zero range has NRMSE 0 when it is reconstructed exactly and
+ * +inf otherwise. */
+int oracle_error_stats(const float *const *orig, const float *const *recon, const uint32_t *perm,
+                       uint64_t n, uint32_t F, double *sum_sq, double *nrmse, double *psnr) {
+    double mean = 0.0;
+    for (uint32_t f = 0; f < F; f++) {
+        double ss = 0.0;
+        for (uint64_t j = 0; j < n; j++) {
+            if (perm && perm[j] >= n) continue;
+            double d = (double)recon[f][j] - (double)orig[f][perm ? perm[j] : j];
+            if (isnan(d)) continue;
+            ss += d * d;
+        }
+        sum_sq[f] = ss;
+        float mm[2];
+        const float *one[1] = {orig[f]};
+        oracle_field_range(one, n, 1, mm);
+        double range = (double)mm[1] - (double)mm[0];
+        double rmse = n ? sqrt(ss / (double)n) : 0.0;
+        nrmse[f] = range > 0.0 ? rmse / range : (rmse == 0.0 ? 0.0 : INFINITY);
+        mean += nrmse[f] * nrmse[f];
+    }
+    mean /= (double)F;
+    *psnr = -20.0 * log10(sqrt(mean));
+    return OR_OK;
+}
+
+/* Structure statistics of a stream: the outliers stored per field (Sec. 4.3
+ * records, counted in coded blocks) and the number of blocks stored raw. */
+int oracle_stream_stats(const uint8_t *in, uint64_t bytes, uint64_t n, uint32_t F,
+                        uint64_t *outliers, uint64_t *raw_blocks) {
+    uint64_t info[7];
+    int rc = oracle_inspect(in, bytes, info);
+    if (rc) return rc;
+    if (info[0] != n || info[1] != F) return OR_EINVAL;
+    if (info[6] != bytes) return OR_ECORRUPT;
+    const uint32_t *w = (const uint32_t *)in;
+    uint32_t B = (uint32_t)info[2];
+    uint64_t nb = info[5];
+    const uint32_t *lt = w + OR_HEADER_WORDS + 2 * nsuper_of(nb) + F;
+    const uint32_t *rec = lt + nb;
+    for (uint32_t f = 0; f < F; f++) outliers[f] = 0;
+    *raw_blocks = 0;
+    for (uint64_t b = 0; b < nb; b++) {
+        uint32_t len = lt[b];
+        uint32_t nn = (uint32_t)((b + 1) * B <= n ? B : n - b * B);
+        if (len < 1) return OR_ECORRUPT;
+        if ((rec[0] & 3u) == 1u) {
+            (*raw_blocks)++;
+        } else {
+            if (len < 2) return OR_ECORRUPT;
+            uint32_t U = rec[0] >> 2, h1 = rec[1];
+            uint64_t pos = 2 + (uint64_t)words_for(U, h1 & 31u) + words_for(U, (h1 >> 5) & 31u);
+            for (uint32_t f = 0; f < F; f++) {
+                if (pos + 2 > len) return OR_ECORRUPT;
+                uint32_t wn = rec[pos + 1];
+                outliers[f] += wn >> 5;
+                pos += 2 + (uint64_t)words_for(nn, wn & 31u) + 2 * (uint64_t)(wn >> 5);
+            }
+            if (pos != len) return OR_ECORRUPT;
+        }
+        rec += len;
+    }
+    return OR_OK;
+}
+
 /* Value-range-relative bound -> absolute bound of one field: rel times the
  * field's range, rounded to float; a bound that would fall below 2^-120
  * (a constant field) becomes rel itself, and one above 2^120 is capped. */

@@ -23,7 +23,8 @@ GPZ_OK, GPZ_EINVAL, GPZ_ENOSPC, GPZ_ECORRUPT, GPZ_EDEVICE, GPZ_ENOMEM, GPZ_EUNSU
 EXPORTS = (
     "gpz_default_params", "gpz_max_compressed_bytes", "gpz_compress_workspace_bytes",
     "gpz_decompress_workspace_bytes", "gpz_compress", "gpz_compress_async", "gpz_decompress",
-    "gpz_decompress_async", "gpz_bound_check", "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
+    "gpz_decompress_async", "gpz_bound_check", "gpz_error_stats", "gpz_stream_stats",
+    "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
     "gpz_set_timing", "gpz_timing_collect", "gpz_strerror", "gpz_default_batch_config",
     "gpz_batch_workspace_bytes", "gpz_batch_create", "gpz_batch_rebind", "gpz_batch_compress",
     "gpz_batch_decompress", "gpz_batch_sizes", "gpz_batch_errors", "gpz_batch_destroy",
@@ -43,7 +44,7 @@ class GpzError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_uint32), ("seg_bits", ctypes.c_uint32),
-                ("key_fields", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("key_fields", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class Job(ctypes.Structure):
@@ -96,6 +97,10 @@ def _lib():
         L.gpz_decompress_async.restype = ctypes.c_int
         L.gpz_bound_check.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp, vp]
         L.gpz_bound_check.restype = ctypes.c_int
+        L.gpz_error_stats.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp, vp, vp]
+        L.gpz_error_stats.restype = ctypes.c_int
+        L.gpz_stream_stats.argtypes = [vp, u64, u64, u32, vp, vp, vp]
+        L.gpz_stream_stats.restype = ctypes.c_int
         L.gpz_field_range.argtypes = [vp, u64, u32, vp, vp]
         L.gpz_field_range.restype = ctypes.c_int
         L.gpz_rel_to_abs.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
@@ -171,14 +176,20 @@ def _check_fields(fields: Sequence, n: Optional[int] = None):
     return n
 
 
+GPZ_FLAG_SINGLE_PASS = 1
+
+
 def params(nfields: int, block_size: int = 1024, seg_bits: int = 3,
-           key_fields: Optional[int] = None) -> Params:
+           key_fields: Optional[int] = None, single_pass: bool = False) -> Params:
+    """Parameters; `single_pass` selects the look-back compaction instead of
+    the paper's encode / scan / copy sequence (same stream)."""
     p = Params()
     _lib().gpz_default_params(ctypes.byref(p), nfields)
     p.block_size = block_size
     p.seg_bits = seg_bits
     if key_fields is not None:
         p.key_fields = key_fields
+    p.flags = GPZ_FLAG_SINGLE_PASS if single_pass else 0
     return p
 
 
@@ -240,10 +251,11 @@ class Compressor:
 
 
 def compress(fields: Sequence, eb, *, block_size: int = 1024, seg_bits: int = 3,
-             key_fields: Optional[int] = None, want_perm: bool = False, stream=None):
+             key_fields: Optional[int] = None, want_perm: bool = False, stream=None,
+             single_pass: bool = False):
     """Compress SoA float32 CUDA tensors; returns (uint8 CUDA tensor, perm or None)."""
     F = len(fields)
-    p = params(F, block_size, seg_bits, key_fields)
+    p = params(F, block_size, seg_bits, key_fields, single_pass)
     c = Compressor(fields[0].numel(), F, p, device=fields[0].device)
     s, perm = c.compress(fields, eb, want_perm=want_perm, stream=stream)
     return s.clone(), (perm.clone() if perm is not None else None)
@@ -294,6 +306,46 @@ def bound_check(orig: Sequence, recon: Sequence, eb, perm=None, stream=None
     return viol, mx
 
 
+def error_stats(orig: Sequence, recon: Sequence, eb, perm=None, stream=None) -> dict:
+    """Bound check plus rate-distortion figures (Sec. 2): per-field violation
+    counts, maximum and summed squared errors, normalized RMSE over each
+    original field's range, and the aggregate PSNR in dB."""
+    F = len(orig)
+    n = _check_fields(orig)
+    _check_fields(recon, n)
+    ebs = _eb_array(eb, F)
+    viol = np.zeros(F, np.uint64)
+    mx = np.zeros(F, np.float64)
+    ss = np.zeros(F, np.float64)
+    rc = _lib().gpz_error_stats(ctypes.cast(_ptr_array(orig), ctypes.c_void_p),
+                                ctypes.cast(_ptr_array(recon), ctypes.c_void_p),
+                                perm.data_ptr() if perm is not None else None, n, F,
+                                ebs.ctypes.data_as(ctypes.c_void_p),
+                                viol.ctypes.data_as(ctypes.c_void_p),
+                                mx.ctypes.data_as(ctypes.c_void_p),
+                                ss.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+    _check(rc, "gpz_error_stats")
+    mm = field_range(orig, stream)
+    rng = mm[:, 1].astype(np.float64) - mm[:, 0].astype(np.float64)
+    rmse = np.sqrt(ss / n) if n else np.zeros(F)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        nrmse = np.where(rng > 0, rmse / np.where(rng > 0, rng, 1.0),
+                         np.where(rmse == 0, 0.0, np.inf))
+        psnr = float(-20.0 * np.log10(np.sqrt(np.mean(nrmse ** 2))))
+    return {"violations": viol, "max_abs_err": mx, "sum_sq": ss, "nrmse": nrmse, "psnr": psnr}
+
+
+def stream_stats(stream_bytes, n: int, nfields: int, stream=None):
+    """(outliers per field, raw blocks) of a stream held in a uint8 CUDA tensor."""
+    out = np.zeros(nfields, np.uint64)
+    raw = np.zeros(1, np.uint64)
+    rc = _lib().gpz_stream_stats(stream_bytes.data_ptr(), stream_bytes.numel(), n, nfields,
+                                 out.ctypes.data_as(ctypes.c_void_p),
+                                 raw.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+    _check(rc, "gpz_stream_stats")
+    return out, int(raw[0])
+
+
 def field_range(fields: Sequence, stream=None) -> np.ndarray:
     F = len(fields)
     n = _check_fields(fields)
@@ -326,12 +378,13 @@ def set_timing(enable: bool):
     _lib().gpz_set_timing(1 if enable else 0)
 
 
-KERNEL_KINDS = ("encode", "scan", "copy", "decode")
+KERNEL_KINDS = ("encode", "prepare", "decode", "scan", "copy")
 
 
 def timing_collect() -> dict:
     """Per-kernel (total ms, launches) recorded since the last collection."""
-    ms = (ctypes.c_double * 4)()
-    cnt = (ctypes.c_uint32 * 4)()
-    _check(_lib().gpz_timing_collect(ms, cnt, 4), "gpz_timing_collect")
+    k = len(KERNEL_KINDS)
+    ms = (ctypes.c_double * k)()
+    cnt = (ctypes.c_uint32 * k)()
+    _check(_lib().gpz_timing_collect(ms, cnt, k), "gpz_timing_collect")
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}

@@ -14,7 +14,7 @@ namespace {
 
 // Optional kernel timing: HIP events recorded around each kernel on the
 // launch stream, collected later by gpz_timing_collect.
-enum { kEncode = 0, kScan = 1, kCopy = 2, kDecode = 3, kKinds = 4 };
+enum { kEncode = 0, kPrepare = 1, kDecode = 2, kScan = 3, kCopy = 4, kKinds = 5 };
 struct TimedLaunch {
     int kind;
     hipEvent_t a, b;
@@ -52,7 +52,7 @@ bool params_ok(uint32_t F, const gpz_params& p) {
     uint32_t B = p.block_size;
     if (B < 64 || B > 4096 || (B & (B - 1)) != 0) return false;
     if (p.key_fields < 1 || p.key_fields > 3 || p.key_fields > F) return false;
-    if (p.seg_bits > 5 || p.reserved != 0) return false;
+    if (p.seg_bits > 5 || (p.flags & ~GPZ_FLAG_SINGLE_PASS) != 0) return false;
     return true;
 }
 
@@ -68,31 +68,38 @@ gpz_params resolve(const gpz_params* p, uint32_t F) {
 uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
 struct CompressWs {
-    uint32_t* temp;
+    uint32_t* temp;     // record slots
+    uint64_t* state;    // look-back word per block
+    uint32_t* ticket;   // block ticket counter (right after the look-back words)
+    uint64_t* total;    // stream size
+    uint64_t clear_words;  // 32-bit words from `state` to clear before a launch
+    // three-step compaction
     uint32_t* lens;
     uint32_t* supsum;
     uint64_t* supoff;
-    uint64_t* total;
     uint32_t slot_words;
     uint64_t bytes;
 };
 
 CompressWs layout(uint64_t n, uint32_t F, uint32_t B, char* base) {
     CompressWs w{};
-    uint64_t nb = nblocks_of(n, B);
+    const uint64_t nb = nblocks_of(n, B), ns = nsuper_of(nb);
     w.slot_words = (uint32_t)((1 + (uint64_t)F * B + 3) & ~uint64_t(3));
     uint64_t o = 0;
     w.temp = reinterpret_cast<uint32_t*>(base + o);
     o = align256(o + nb * w.slot_words * 4ull);
-    w.lens = reinterpret_cast<uint32_t*>(base + o);
-    o = align256(o + nb * 4ull);
-    const uint64_t ns = nsuper_of(nb);
-    w.supsum = reinterpret_cast<uint32_t*>(base + o);
-    o = align256(o + ns * 4ull);
+    // look-back words, ticket, total and the superblock sums are contiguous:
+    // one fill clears what either compaction needs zeroed
+    w.state = reinterpret_cast<uint64_t*>(base + o);
+    w.ticket = reinterpret_cast<uint32_t*>(base + o + nb * 8);
+    w.total = reinterpret_cast<uint64_t*>(base + o + nb * 8 + 8);
+    w.supsum = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 16);
+    w.clear_words = 2 * nb + 4 + ns;
+    o = align256(o + nb * 8 + 16 + ns * 4);
     w.supoff = reinterpret_cast<uint64_t*>(base + o);
-    o = align256(o + ns * 8ull);
-    w.total = reinterpret_cast<uint64_t*>(base + o);
-    o = align256(o + 64);
+    o = align256(o + ns * 8);
+    w.lens = reinterpret_cast<uint32_t*>(base + o);
+    o = align256(o + nb * 4);
     w.bytes = o;
     return w;
 }
@@ -132,16 +139,11 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     CompressWs w = layout(n, F, B, ws);
 
     EncodeArgs ea{};
-    ScanArgs sa{};
-    CopyArgs ca{};
     for (uint32_t f = 0; f < F; f++) {
         ea.x[f] = n ? h_fields[f] : nullptr;
         ea.eb[f] = h_eb[f];
         ea.twoeb[f] = 2.0f * h_eb[f];
         ea.inv[f] = 1.0f / ea.twoeb[f];
-        uint32_t bits;
-        memcpy(&bits, &h_eb[f], 4);
-        sa.eb_bits[f] = bits;
     }
     ea.n = n;
     ea.F = F;
@@ -151,46 +153,60 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     ea.nblocks = (uint32_t)nb;
     ea.slot_words = w.slot_words;
     ea.temp = w.temp;
+    ea.state = w.state;
+    ea.ticket = w.ticket;
+    ea.perm = d_perm;
+    ea.out = static_cast<uint32_t*>(d_out);
+    ea.capacity = cap;
+    ea.prefix = prefix_words(n, F, B);
+    ea.total_bytes = w.total;
+    ea.ext_bytes = d_out_bytes;
+    const bool single = (p.flags & GPZ_FLAG_SINGLE_PASS) != 0;
     ea.lens = w.lens;
     ea.supsum = w.supsum;
-    ea.perm = d_perm;
-
-    sa.supsum = w.supsum;
-    sa.supoff = w.supoff;
-    sa.total_bytes = w.total;
-    sa.ext_bytes = d_out_bytes;
-    sa.nsuper = (uint32_t)nsuper_of(nb);
-    sa.prefix = prefix_words(n, F, B);
-    sa.out = static_cast<uint32_t*>(d_out);
-    sa.capacity = cap;
-    sa.n = n;
-    sa.F = F;
-    sa.B = B;
-    sa.K = p.seg_bits;
-    sa.KF = p.key_fields;
-    sa.nblocks = (uint32_t)nb;
-
-    ca.temp = w.temp;
-    ca.lens = w.lens;
-    ca.supoff = w.supoff;
-    ca.total_bytes = w.total;
-    ca.out = static_cast<uint32_t*>(d_out);
-    ca.capacity = cap;
-    ca.slot_words = w.slot_words;
-    ca.nblocks = (uint32_t)nb;
-    ca.F = F;
 
     Timer tm(s);
-    int rc = to_status(launch_fill_u32(w.supsum, 0u, nsuper_of(nb), s));
+    tm.begin(kPrepare);
+    int rc = to_status(
+        launch_fill_u32(reinterpret_cast<uint32_t*>(w.state), 0u, w.clear_words, s));
+    tm.end();
     tm.begin(kEncode);
-    if (rc == GPZ_OK) rc = to_status(launch_encode(ea, s));
+    if (rc == GPZ_OK) rc = to_status(launch_encode(ea, single, s));
     tm.end();
-    tm.begin(kScan);
-    if (rc == GPZ_OK) rc = to_status(launch_scan(sa, s));
-    tm.end();
-    tm.begin(kCopy);
-    if (rc == GPZ_OK) rc = to_status(launch_copy(ca, s));
-    tm.end();
+    if (!single) {
+        ScanArgs sa{};
+        CopyArgs ca{};
+        for (uint32_t f = 0; f < F; f++) memcpy(&sa.eb_bits[f], &h_eb[f], 4);
+        sa.supsum = w.supsum;
+        sa.supoff = w.supoff;
+        sa.total_bytes = w.total;
+        sa.ext_bytes = d_out_bytes;
+        sa.nsuper = (uint32_t)nsuper_of(nb);
+        sa.prefix = ea.prefix;
+        sa.out = ea.out;
+        sa.capacity = cap;
+        sa.n = n;
+        sa.F = F;
+        sa.B = B;
+        sa.K = p.seg_bits;
+        sa.KF = p.key_fields;
+        sa.nblocks = (uint32_t)nb;
+        ca.temp = w.temp;
+        ca.lens = w.lens;
+        ca.supoff = w.supoff;
+        ca.total_bytes = w.total;
+        ca.out = ea.out;
+        ca.capacity = cap;
+        ca.slot_words = w.slot_words;
+        ca.nblocks = (uint32_t)nb;
+        ca.F = F;
+        tm.begin(kScan);
+        if (rc == GPZ_OK) rc = to_status(launch_scan(sa, s));
+        tm.end();
+        tm.begin(kCopy);
+        if (rc == GPZ_OK) rc = to_status(launch_copy(ca, s));
+        tm.end();
+    }
     if (sync) {
         uint64_t total = 0;
         if (rc == GPZ_OK) rc = to_status(hipMemcpyAsync(&total, w.total, 8, hipMemcpyDeviceToHost, s));
@@ -211,7 +227,7 @@ void gpz_default_params(gpz_params* p, uint32_t nfields) {
     p->block_size = 1024;
     p->seg_bits = 3;
     p->key_fields = nfields < 3 ? (nfields ? nfields : 1) : 3;
-    p->reserved = 0;
+    p->flags = 0;
 }
 
 uint64_t gpz_max_compressed_bytes(uint64_t n, uint32_t nfields, const gpz_params* pp) {
@@ -336,24 +352,27 @@ int gpz_decompress_async(const void* d_in, uint64_t in_bytes, float* const* h_fi
                            static_cast<hipStream_t>(stream), false);
 }
 
-int gpz_bound_check(const float* const* h_orig, const float* const* h_recon,
+int gpz_error_stats(const float* const* h_orig, const float* const* h_recon,
                     const uint32_t* d_perm, uint64_t n, uint32_t nfields, const float* h_eb,
-                    uint64_t* h_violations, double* h_max_abs_err, void* stream) {
+                    uint64_t* h_violations, double* h_max_abs_err, double* h_sum_sq_err,
+                    void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (nfields < 1 || nfields > kMaxFields || !h_eb || !h_violations || !h_max_abs_err)
         return GPZ_EINVAL;
     if (n > 0 && (!h_orig || !h_recon)) return GPZ_EINVAL;
     for (uint32_t f = 0; n > 0 && f < nfields; f++)
         if (!h_orig[f] || !h_recon[f]) return GPZ_EINVAL;
+    // counts, maximum-error bits and sums of squares: 3 x 8 bytes per field
     unsigned long long* acc = nullptr;
-    if (hipMalloc(&acc, 16ull * nfields) != hipSuccess) return GPZ_ENOMEM;
-    int rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, 4ull * nfields, s));
+    if (hipMalloc(&acc, 24ull * nfields) != hipSuccess) return GPZ_ENOMEM;
+    double* sumsq = h_sum_sq_err ? reinterpret_cast<double*>(acc + 2 * nfields) : nullptr;
+    int rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, 6ull * nfields, s));
     if (rc == GPZ_OK && n > 0)
         rc = to_status(launch_bound_check(h_orig, h_recon, d_perm, n, nfields, h_eb, acc,
-                                          acc + nfields, s));
-    std::vector<unsigned long long> h(2 * nfields);
+                                          acc + nfields, sumsq, s));
+    std::vector<unsigned long long> h(3 * nfields);
     if (rc == GPZ_OK)
-        rc = to_status(hipMemcpyAsync(h.data(), acc, 16ull * nfields, hipMemcpyDeviceToHost, s));
+        rc = to_status(hipMemcpyAsync(h.data(), acc, 24ull * nfields, hipMemcpyDeviceToHost, s));
     if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
     (void)hipFree(acc);
     if (rc) return rc;
@@ -362,7 +381,54 @@ int gpz_bound_check(const float* const* h_orig, const float* const* h_recon,
         double d;
         memcpy(&d, &h[nfields + f], 8);
         h_max_abs_err[f] = d;
+        if (h_sum_sq_err) {
+            memcpy(&d, &h[2 * nfields + f], 8);
+            h_sum_sq_err[f] = d;
+        }
     }
+    return GPZ_OK;
+}
+
+int gpz_bound_check(const float* const* h_orig, const float* const* h_recon,
+                    const uint32_t* d_perm, uint64_t n, uint32_t nfields, const float* h_eb,
+                    uint64_t* h_violations, double* h_max_abs_err, void* stream) {
+    return gpz_error_stats(h_orig, h_recon, d_perm, n, nfields, h_eb, h_violations,
+                           h_max_abs_err, nullptr, stream);
+}
+
+int gpz_stream_stats(const void* d_in, uint64_t in_bytes, uint64_t n, uint32_t nfields,
+                     uint64_t* h_outliers, uint64_t* h_raw_blocks, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!d_in || nfields < 1 || nfields > kMaxFields || !h_outliers || !h_raw_blocks)
+        return GPZ_EINVAL;
+    if (in_bytes < 4 * kHeaderWords) return GPZ_ECORRUPT;
+    uint32_t hdr[kHeaderWords];
+    if (hipMemcpyAsync(hdr, d_in, sizeof(hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return GPZ_EDEVICE;
+    gpz_info info;
+    int rc = gpz_inspect(hdr, sizeof(hdr), &info);
+    if (rc) return rc;
+    if (info.n != n || info.nfields != nfields) return GPZ_EINVAL;
+    const uint64_t prefix = prefix_words(n, nfields, info.block_size);
+    if (4 * prefix > in_bytes) return GPZ_ECORRUPT;
+    // outliers per field, raw blocks, error flag
+    unsigned long long* acc = nullptr;
+    if (hipMalloc(&acc, 8ull * (nfields + 2)) != hipSuccess) return GPZ_ENOMEM;
+    uint32_t* err = reinterpret_cast<uint32_t*>(acc + nfields + 1);
+    rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, 2ull * (nfields + 2), s));
+    if (rc == GPZ_OK)
+        rc = to_status(launch_stream_stats(static_cast<const uint32_t*>(d_in), in_bytes / 4, n,
+                                           nfields, info.block_size, acc, acc + nfields, err, s));
+    std::vector<unsigned long long> h(nfields + 2);
+    if (rc == GPZ_OK)
+        rc = to_status(hipMemcpyAsync(h.data(), acc, 8ull * (nfields + 2), hipMemcpyDeviceToHost, s));
+    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    (void)hipFree(acc);
+    if (rc) return rc;
+    if (h[nfields + 1] & 0xFFFFFFFFull) return GPZ_ECORRUPT;
+    for (uint32_t f = 0; f < nfields; f++) h_outliers[f] = h[f];
+    *h_raw_blocks = h[nfields];
     return GPZ_OK;
 }
 

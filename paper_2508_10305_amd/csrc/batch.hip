@@ -68,7 +68,7 @@ int validate_params(const gpz_params& p) {
                 (p.block_size & (p.block_size - 1)) == 0)
                    ? GPZ_EUNSUPPORTED
                    : GPZ_EINVAL;
-    if (p.seg_bits > 5 || p.reserved != 0 || p.key_fields < 1 || p.key_fields > 3)
+    if (p.seg_bits > 5 || p.flags != 0 || p.key_fields < 1 || p.key_fields > 3)
         return GPZ_EINVAL;
     return GPZ_OK;
 }
@@ -335,7 +335,7 @@ int gpz_batch_create(gpz_batch** out, const gpz_job* jobs, uint32_t njobs, const
     b->shape.B = B;
     b->shape.grid = c.grid;
     b->shape.scan_grid = b->max_jobs < 256 ? b->max_jobs : 256;
-    b->shape.copy_grid = c.grid / 4 ? c.grid / 4 : 1;
+    b->shape.copy_grid = c.grid;  // 4-wave workgroups: 4 x grid waves copying
     b->shape.tail_grid = b->max_jobs < 64 ? b->max_jobs : 64;
     const uint32_t mj = b->max_jobs;
     const uint64_t mb = b->max_blocks, ms = b->max_super;

@@ -58,9 +58,13 @@ struct DecodeSmem {
     static constexpr uint32_t kRle = (B * 15) / 32 + (B * 12) / 32 + 4;
     static constexpr uint32_t kWords = ((kPay > kRle ? kPay : kRle) + 3) & ~3u;  // 16-byte multiple
     static constexpr uint32_t kPadB = 64 * (ITEMS + 4);
-    uint32_t words[kWords];
-    uint32_t keys[kPadB];
-    uint32_t ystage[B];
+    // The packed words, the key expansion and the outlier staging are never
+    // live at the same time: one region serves all three (barriers between
+    // the phases), which keeps the workgroup's LDS small enough for high
+    // occupancy.
+    static constexpr uint32_t kA = kWords > kPadB ? kWords : kPadB;
+    static constexpr uint32_t kBuf = kA > B ? kA : B;
+    uint32_t buf[kBuf];
 };
 
 template <int ITEMS>
@@ -68,9 +72,9 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
                                              DecodeSmem<ITEMS>& sm) {
     constexpr uint32_t B = 64 * ITEMS;
     constexpr uint32_t G = ITEMS / 4;  // 16-byte groups per lane
-    uint32_t* words = sm.words;
-    uint32_t* keys = sm.keys;
-    uint32_t* ystage = sm.ystage;
+    uint32_t* words = sm.buf;
+    uint32_t* keys = sm.buf;
+    uint32_t* ystage = sm.buf;
 
     const uint32_t lane = threadIdx.x;
     const uint64_t base = (uint64_t)b * B;
@@ -175,6 +179,7 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
     }
     // mark run starts with their ID; IDs increase with position, so a prefix
     // maximum over positions gives every position its ID
+    __syncthreads();  // the packed gaps and counts are read; `keys` reuses them
     for (uint32_t p = lane; p < B; p += 64) keys[pad_addr<ITEMS>(p)] = 0u;
     __syncthreads();
     {
@@ -264,8 +269,9 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
                 y[4 * g + e] = f2u(__builtin_fmaf((float)q, twoeb, lo));
             }
         if (nout) {
-            // patch outliers through LDS
+            // patch outliers through LDS (the staging reuses `words`)
             const uint32_t* ol = rec + pos + 2 + pw;
+            __syncthreads();
 #pragma unroll
             for (int g = 0; g < G; g++)
                 reinterpret_cast<uint4*>(ystage)[64 * g + lane] =
@@ -332,7 +338,7 @@ __global__ __launch_bounds__(64) void decode_batch(const DecodeArgs* __restrict_
     for (;;) {
         uint32_t item = 0;
         if (threadIdx.x == 0) item = atomicAdd(L->counter + 1, tile);
-        item = (uint32_t)__shfl((int)item, 0);
+        item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
         if (item >= total) break;
         const uint32_t end = min(item + tile, total);
         for (uint32_t g = item; g < end; g++) {

@@ -1,7 +1,11 @@
 // Block encoder: GPZ stages 1-3 (Sec. 4.1 quantization, Sec. 4.2 in-block
 // sort, Sec. 4.3 run-length / delta / fixed-length coding) for one block of
 // B particles per wave64, writing the block's record into its workspace slot
-// (first step of the Sec. 4.4 compaction).
+// and its length (first step of the Sec. 4.4 compaction; the scan and copy
+// kernels finish it).  An alternative single-pass compaction is also built:
+// the block publishes its length, finds its offset in the stream by a
+// decoupled look-back over the lengths of the blocks before it, and copies
+// its record there itself.
 //
 // Lane layout: lane l owns the ITEMS = B/64 consecutive particles
 // [l*ITEMS, (l+1)*ITEMS) of its block ("blocked"), so per-lane sequential
@@ -219,7 +223,118 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
     __syncthreads();
 }
 
-template <int ITEMS, bool FULL>
+// ------------------------------------------------------------ compaction
+// Look-back word of a block: (value << 2) | flag, flag 1 = the block's own
+// record length is known, 2 = the inclusive prefix (words of all records up
+// to and including this block) is known, 0 = nothing yet.
+constexpr uint64_t kFlagLen = 1u, kFlagIncl = 2u;
+
+__device__ __forceinline__ uint64_t load_state(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_state(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Exclusive prefix (in words) of the record lengths of blocks 0..b-1.  Every
+// block with a smaller index was started before this one (tickets), so the
+// waits below always end.  Lane i inspects block top - i; the
+// window moves back 64 blocks at a time until it meets an inclusive prefix.
+__device__ __forceinline__ uint64_t exclusive_offset(uint64_t* state, uint32_t b, uint32_t len,
+                                                     uint32_t lane) {
+    if (lane == 0) store_state(state + b, ((uint64_t)len << 2) | (b == 0 ? kFlagIncl : kFlagLen));
+    if (b == 0) return 0;
+    uint64_t excl = 0;
+    int64_t top = (int64_t)b - 1;
+    for (;;) {
+        const int64_t p = top - (int64_t)lane;
+        const uint64_t st = p >= 0 ? load_state(state + p) : kFlagIncl;
+        const uint64_t flag = st & 3u;
+        const uint64_t incl = __ballot(flag == kFlagIncl);
+        const uint64_t pending = __ballot(flag == 0);
+        // lanes up to and including the nearest inclusive prefix
+        const uint64_t upto = incl ? ((incl & (~incl + 1)) << 1) - 1 : ~0ull;
+        if (pending & upto) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_sum_u64(((upto >> lane) & 1u) ? (st >> 2) : 0u);
+        if (incl) break;
+        top -= 64;
+    }
+    if (lane == 0) store_state(state + b, ((excl + len) << 2) | kFlagIncl);
+    return excl;
+}
+
+// Stream header and error-bound table (format v1).
+__device__ __forceinline__ void write_header(const EncodeArgs& a, uint32_t lane) {
+    uint32_t* out = a.out;
+    if (lane == 0) {
+        out[0] = kMagic;
+        out[1] = kVersion;
+        out[2] = (uint32_t)(a.n & 0xFFFFFFFFu);
+        out[3] = (uint32_t)(a.n >> 32);
+        out[4] = a.F;
+        out[5] = a.B;
+        out[6] = a.K | (a.KF << 8);
+        out[7] = a.nblocks;
+    }
+    uint32_t* ebt = out + kHeaderWords + 2 * nsuper_of(a.nblocks);
+    for (uint32_t f = lane; f < a.F; f += 64) ebt[f] = f2u(a.eb[f]);
+}
+
+__device__ __forceinline__ void publish_size(const EncodeArgs& a, uint64_t total, uint32_t lane) {
+    if (lane == 0) {
+        *a.total_bytes = total;
+        if (a.ext_bytes) *a.ext_bytes = total;
+    }
+    if (total <= a.capacity) write_header(a, lane);
+}
+
+// Block b's record (len words at rec) goes to its final offset; the block
+// also writes its length-table entry, the superblock entry when it opens a
+// superblock, and, as the last block, the stream size and header.  Nothing
+// is written past the output capacity.
+__device__ __forceinline__ void place_record(const EncodeArgs& a, uint32_t b, const uint32_t* rec,
+                                             uint32_t len, uint32_t lane) {
+    __syncthreads();  // the record's stores by all lanes before they are read back
+    const uint64_t excl = exclusive_offset(a.state, b, len, lane);
+    const uint64_t capw = a.capacity / 4;
+    const uint64_t sup_at = kHeaderWords;
+    const uint64_t lt_at = kHeaderWords + 2 * nsuper_of(a.nblocks) + a.F;
+    uint32_t* out = a.out;
+    if (lane == 0) {
+        if (lt_at + b < capw) out[lt_at + b] = len;
+        if (b % kSuper == 0) {
+            const uint64_t at = sup_at + 2 * (b / kSuper);
+            if (at + 1 < capw) {
+                out[at] = (uint32_t)(excl & 0xFFFFFFFFu);
+                out[at + 1] = (uint32_t)(excl >> 32);
+            }
+        }
+    }
+    const uint64_t off = a.prefix + excl;
+    if (off + len <= capw) {
+        uint32_t* dst = out + off;
+        for (uint32_t k = lane; k < len; k += 256) {
+            uint32_t v[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) v[i] = k + 64 * i < len ? rec[k + 64 * i] : 0u;
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                if (k + 64 * i < len) dst[k + 64 * i] = v[i];
+        }
+    }
+    if (b == a.nblocks - 1) publish_size(a, 4 * (off + len), lane);
+}
+
+template <int ITEMS, bool FULL, bool SINGLE>
 __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, uint32_t nb,
                                              uint32_t* kvbuf, uint32_t* work) {
     constexpr uint32_t B = 64 * ITEMS;
@@ -230,6 +345,14 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     const uint32_t cap = 1 + F * nb;  // raw record length
 
     // ---- Stage 1 (Sec. 4.1): key axes -- block minimum, grid index, segment shift
+    // The loads of the key fields and of the first other field are issued
+    // together, so the block waits for memory once rather than once per field.
+    float xk[3][ITEMS];
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++)
+        if ((uint32_t)ax < KF) load_block<ITEMS, FULL>(a.x[ax], base, nb, lane, xk[ax]);
+    float xnext[ITEMS];
+    if (KF < F) load_block<ITEMS, FULL>(a.x[KF], base, nb, lane, xnext);
     uint32_t qk[3][ITEMS];
     float lok[3];
     uint32_t sk[3];
@@ -238,10 +361,8 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         sk[ax] = 0;
         lok[ax] = 0.0f;
         if ((uint32_t)ax < KF) {
-            float x[ITEMS];
-            load_block<ITEMS, FULL>(a.x[ax], base, nb, lane, x);
-            lok[ax] = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[ax], a.twoeb[ax], a.eb[ax],
-                                                  qk[ax]);
+            lok[ax] = quantize_field<ITEMS, FULL>(xk[ax], nb, lane, a.inv[ax], a.twoeb[ax],
+                                                  a.eb[ax], qk[ax]);
             uint32_t m = 0;
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) m = max(m, qk[ax][j] & 0xFFFFFFu);
@@ -365,8 +486,11 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
                 const uint32_t s = f == 0 ? sk[0] : (f == 1 ? sk[1] : sk[2]);
                 mask = (1u << s) - 1u;
             } else {
+                // this field was loaded one field ahead; start the next one
                 float x[ITEMS];
-                load_block<ITEMS, FULL>(a.x[f], base, nb, lane, x);
+#pragma unroll
+                for (int j = 0; j < ITEMS; j++) x[j] = xnext[j];
+                if (f + 1 < F) load_block<ITEMS, FULL>(a.x[f + 1], base, nb, lane, xnext);
                 lo = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[f], a.twoeb[f], a.eb[f], q);
                 mask = 0xFFFFFFu;
             }
@@ -439,7 +563,9 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             for (uint32_t i = lane; i < nb; i += 64) dst[i] = f2u(xf[i]);
         }
     }
-    if (lane == 0) {
+    if (SINGLE) {
+        place_record(a, b, rec, raw ? cap : pos, lane);
+    } else if (lane == 0) {
         const uint32_t len = raw ? cap : pos;
         a.lens[b] = len;
         atomicAdd(&a.supsum[b / kSuper], len);  // order-independent sum
@@ -453,22 +579,55 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     }
 }
 
+template <int ITEMS>
+struct EncodeSmem {
+    static constexpr uint32_t B = 64 * ITEMS;
+    static constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
+    static constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
+    static constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
+    __align__(16) uint32_t kvbuf[kKvWords];
+    __align__(16) uint32_t work[kWorkWords];
+};
+
+// Three-step compaction: one workgroup per block, block index = workgroup
+// index.  Full blocks and the partial last block run in separate kernels so
+// that the full-block code carries no bounds checks.
 template <int ITEMS, bool FULL>
-__global__ __launch_bounds__(64) void encode_blocks(EncodeArgs a, uint32_t first_block) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_blocks(EncodeArgs a, uint32_t first_block) {
     constexpr uint32_t B = 64 * ITEMS;
-    constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
-    constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
-    constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
-    __shared__ __align__(16) uint32_t kvbuf[kKvWords];
-    __shared__ __align__(16) uint32_t work[kWorkWords];
+    __shared__ EncodeSmem<ITEMS> sm;
     const uint32_t b = first_block + blockIdx.x;
     const uint64_t base = (uint64_t)b * B;
     const uint32_t nb = (uint32_t)((a.n - base) < B ? (a.n - base) : B);
-    encode_block<ITEMS, FULL>(a, b, nb, kvbuf, work);
+    encode_block<ITEMS, FULL, false>(a, b, nb, sm.kvbuf, sm.work);
+}
+
+// Single-pass compaction: blocks are numbered by a ticket taken when the
+// workgroup starts, so a block only ever waits on blocks already running.
+template <int ITEMS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_blocks_single(EncodeArgs a) {
+    constexpr uint32_t B = 64 * ITEMS;
+    __shared__ EncodeSmem<ITEMS> sm;
+    uint32_t t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(a.ticket, 1u);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+    const uint64_t left = a.n - (uint64_t)b * B;
+    if (left >= B) encode_block<ITEMS, true, true>(a, b, B, sm.kvbuf, sm.work);
+    else encode_block<ITEMS, false, true>(a, b, (uint32_t)left, sm.kvbuf, sm.work);
+}
+
+// Single pass, a snapshot with no particles: header only.
+__global__ __launch_bounds__(64) void empty_stream(EncodeArgs a) {
+    publish_size(a, 4 * a.prefix, threadIdx.x);
 }
 
 template <int ITEMS>
-void launch_encode_items(const EncodeArgs& a, hipStream_t s) {
+void launch_encode_items(const EncodeArgs& a, bool single_pass, hipStream_t s) {
+    if (single_pass) {
+        if (a.nblocks) hipLaunchKernelGGL(encode_blocks_single<ITEMS>, dim3(a.nblocks), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL(empty_stream, dim3(1), dim3(64), 0, s, a);
+        return;
+    }
     // every block but a partial last one runs the bounds-check-free kernel
     const uint32_t nfull = (uint32_t)(a.n / (64 * ITEMS));
     if (nfull) hipLaunchKernelGGL((encode_blocks<ITEMS, true>), dim3(nfull), dim3(64), 0, s, a, 0u);
@@ -479,25 +638,21 @@ void launch_encode_items(const EncodeArgs& a, hipStream_t s) {
 // Persistent encoder over the full blocks of many snapshots: each wave takes
 // `tile` consecutive blocks from a device work queue until it is empty.
 template <int ITEMS>
-__global__ __launch_bounds__(64) void encode_batch(const EncodeArgs* __restrict__ jobs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_batch(const EncodeArgs* __restrict__ jobs,
                                                    const BatchLaunch* __restrict__ L) {
     constexpr uint32_t B = 64 * ITEMS;
-    constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
-    constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
-    constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
-    __shared__ __align__(16) uint32_t kvbuf[kKvWords];
-    __shared__ __align__(16) uint32_t work[kWorkWords];
+    __shared__ EncodeSmem<ITEMS> sm;
     const uint32_t total = L->total_full, njobs = L->njobs, tile = L->tile;
     const uint32_t* prefix = L->full_prefix;
     for (;;) {
         uint32_t item = 0;
         if (threadIdx.x == 0) item = atomicAdd(L->counter, tile);
-        item = (uint32_t)__shfl((int)item, 0);
+        item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
         if (item >= total) break;
         const uint32_t end = min(item + tile, total);
         for (uint32_t g = item; g < end; g++) {
             const uint32_t j = find_job(prefix, njobs, g);
-            encode_block<ITEMS, true>(jobs[j], g - prefix[j], B, kvbuf, work);
+            encode_block<ITEMS, true, false>(jobs[j], g - prefix[j], B, sm.kvbuf, sm.work);
             __syncthreads();
         }
     }
@@ -505,20 +660,16 @@ __global__ __launch_bounds__(64) void encode_batch(const EncodeArgs* __restrict_
 
 // The partial last block of each snapshot that has one.
 template <int ITEMS>
-__global__ __launch_bounds__(64) void encode_batch_tails(const EncodeArgs* __restrict__ jobs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_batch_tails(const EncodeArgs* __restrict__ jobs,
                                                          const BatchLaunch* __restrict__ L) {
     constexpr uint32_t B = 64 * ITEMS;
-    constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
-    constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
-    constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
-    __shared__ __align__(16) uint32_t kvbuf[kKvWords];
-    __shared__ __align__(16) uint32_t work[kWorkWords];
+    __shared__ EncodeSmem<ITEMS> sm;
     const uint32_t ntail = L->ntail;
     for (uint32_t t = blockIdx.x; t < ntail; t += gridDim.x) {
         const EncodeArgs& a = jobs[L->tail_jobs[t]];
         const uint32_t b = a.nblocks - 1;
         const uint32_t nb = (uint32_t)(a.n - (uint64_t)b * B);
-        encode_block<ITEMS, false>(a, b, nb, kvbuf, work);
+        encode_block<ITEMS, false, false>(a, b, nb, sm.kvbuf, sm.work);
         __syncthreads();
     }
 }
@@ -544,13 +695,12 @@ hipError_t launch_encode_batch(const EncodeArgs* jobs, const BatchLaunch* L, con
     return hipGetLastError();
 }
 
-hipError_t launch_encode(const EncodeArgs& a, hipStream_t s) {
-    if (a.nblocks == 0) return hipSuccess;
+hipError_t launch_encode(const EncodeArgs& a, bool single_pass, hipStream_t s) {
     switch (a.B) {
-        case 256: launch_encode_items<4>(a, s); break;
-        case 512: launch_encode_items<8>(a, s); break;
-        case 1024: launch_encode_items<16>(a, s); break;
-        case 2048: launch_encode_items<32>(a, s); break;
+        case 256: launch_encode_items<4>(a, single_pass, s); break;
+        case 512: launch_encode_items<8>(a, single_pass, s); break;
+        case 1024: launch_encode_items<16>(a, single_pass, s); break;
+        case 2048: launch_encode_items<32>(a, single_pass, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -38,13 +38,23 @@ struct EncodeArgs {
     uint64_t n;
     uint32_t F, K, KF, B;
     uint32_t nblocks;
-    uint32_t slot_words;  // record slot stride in the workspace (>= 1 + F*B)
-    uint32_t* temp;       // nblocks record slots
-    uint32_t* lens;       // record length (words) per block
-    uint32_t* supsum;     // per 64-block superblock: sum of record lengths (zeroed before)
-    uint32_t* perm;       // nullable: n global input indices
+    uint32_t slot_words;   // record slot stride in the workspace (>= 1 + F*B)
+    uint32_t* temp;        // nblocks record slots
+    uint64_t* state;       // single pass: nblocks look-back words, zero before the launch
+    uint32_t* ticket;      // single pass: block ticket counter, zero before the launch
+    uint32_t* perm;        // nullable: n global input indices
+    // three-step compaction: lengths for the scan and copy kernels
+    uint32_t* lens;        // record length (words) per block
+    uint32_t* supsum;      // per 64-block superblock: sum of record lengths (zeroed before)
+    // single-pass compaction: records go straight to their final offsets
+    uint32_t* out;
+    uint64_t capacity;     // bytes of out
+    uint64_t prefix;       // words before the record area
+    uint64_t* total_bytes; // stream size, written by the last block
+    uint64_t* ext_bytes;   // nullable second destination of the size
 };
 
+// Three-step compaction (Sec. 4.4): scan of the superblock sums, then the copy.
 struct ScanArgs {
     const uint32_t* supsum; // record words per superblock
     uint64_t* supoff;       // exclusive prefix of supsum (words, inside the record area)
@@ -180,7 +190,9 @@ __device__ __forceinline__ float u2f(uint32_t u) { return __uint_as_float(u); }
 
 // ------------------------------------------------------------ launchers
 
-hipError_t launch_encode(const EncodeArgs& a, hipStream_t s);
+// single_pass: one launch that also places the records (look-back);
+// otherwise records and lengths for launch_scan / launch_copy.
+hipError_t launch_encode(const EncodeArgs& a, bool single_pass, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_copy(const CopyArgs& a, hipStream_t s);
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t s);
@@ -188,7 +200,10 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t count, hipStrea
 hipError_t launch_bound_check(const float* const* orig, const float* const* recon,
                               const uint32_t* perm, uint64_t n, uint32_t F, const float* eb,
                               unsigned long long* viol, unsigned long long* maxerr_bits,
-                              hipStream_t s);
+                              double* sumsq, hipStream_t s);
+hipError_t launch_stream_stats(const uint32_t* in, uint64_t in_words, uint64_t n, uint32_t F,
+                               uint32_t B, unsigned long long* outliers, unsigned long long* raw,
+                               uint32_t* err, hipStream_t s);
 hipError_t launch_field_range(const float* const* x, uint64_t n, uint32_t F, int* keys,
                               hipStream_t s);
 

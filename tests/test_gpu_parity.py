@@ -48,6 +48,11 @@ def check_case(gpz, orc, host, eb, B=1024, K=3, KF=None, label=""):
         bad = np.nonzero(w1 != w2)[0]
         raise AssertionError(f"{label}: {bad.size} words differ, first at word {bad[0]}")
     assert (perm.cpu().numpy().astype(np.uint32) == ref_perm).all(), f"{label}: perm"
+    # the single-pass (look-back) compaction writes the same stream
+    got1, perm1 = gpz.compress(dev, eb, block_size=B, seg_bits=K, key_fields=KF, want_perm=True,
+                               single_pass=True)
+    assert torch.equal(got1, got), f"{label}: single-pass compaction stream differs"
+    assert torch.equal(perm1, perm), f"{label}: single-pass perm differs"
     out = gpz.decompress(got, n, F)
     ref_out = orc.decompress(ref, n, F)
     for f in range(F):
@@ -159,22 +164,30 @@ def test_gpu_decodes_oracle_stream_and_rejects_corruption(gpz, orc):
         gpz.decompress(torch.from_numpy(bad.view(np.uint8)).cuda(), 100_000, 3)
 
 
-def test_enospc_reports_size(gpz, orc):
-    host = [np.random.default_rng(2).random(10_000).astype(np.float32) for _ in range(3)]
+@pytest.mark.parametrize("single_pass", [False, True])
+@pytest.mark.parametrize("short", [1, 4097, None])
+def test_enospc_reports_size(gpz, orc, single_pass, short):
+    """Too small an output buffer: GPZ_ENOSPC with the size needed, and not a
+    byte written past the capacity (sentinel bytes behind it stay intact)."""
+    n = 10_000
+    host = [np.random.default_rng(2).random(n).astype(np.float32) for _ in range(3)]
     dev = to_dev(host)
     ref, _ = orc.compress(host, 1e-3)
     L = gpz.lib()
-    p = gpz.params(3)
-    out = torch.empty(ref.size - 1, dtype=torch.uint8, device="cuda")
-    ws = torch.empty(gpz.compress_workspace_bytes(10_000, 3, p), dtype=torch.uint8, device="cuda")
+    p = gpz.params(3, single_pass=single_pass)
+    cap = ref.size - short if short else 40  # None: not even the header fits
+    buf = torch.full((cap + 8192,), 0xA5, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(gpz.compress_workspace_bytes(n, 3, p), dtype=torch.uint8, device="cuda")
     nbytes = ctypes.c_uint64(0)
     ptrs = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in dev])
     ebs = np.full(3, 1e-3, np.float32)
-    rc = L.gpz_compress(ctypes.cast(ptrs, ctypes.c_void_p), 10_000, 3,
-                        ebs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), out.data_ptr(),
-                        out.numel(), ctypes.byref(nbytes), None, ws.data_ptr(), ws.numel(),
+    say(f"[case] enospc single_pass={single_pass} cap={cap}")
+    rc = L.gpz_compress(ctypes.cast(ptrs, ctypes.c_void_p), n, 3,
+                        ebs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), buf.data_ptr(),
+                        cap, ctypes.byref(nbytes), None, ws.data_ptr(), ws.numel(),
                         torch.cuda.current_stream().cuda_stream)
     assert rc == gpz.GPZ_ENOSPC and nbytes.value == ref.size
+    assert (buf[cap:].cpu().numpy() == 0xA5).all(), "bytes written past the capacity"
 
 
 def test_field_range_parity(gpz, orc):
@@ -187,6 +200,51 @@ def test_field_range_parity(gpz, orc):
     g = gpz.field_range(dev)
     r = orc.field_range(host)
     assert (g.view(np.uint32) == r.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("offset", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [1, 3, 7, 64, 1001, 262_147])
+def test_field_range_unaligned_views(gpz, orc, offset, n):
+    """Views that start off a 16-byte boundary, with the extremes placed in
+    the unaligned head and the tail."""
+    rng = np.random.default_rng(n + offset)
+    host = [rng.standard_normal(n + offset).astype(np.float32) for _ in range(2)]
+    host[0][offset] = 1e30  # first element of the view: head when offset != 0
+    host[1][-1] = -1e30     # last element: tail
+    dev = [t[offset:] for t in to_dev(host)]
+    g = gpz.field_range(dev)
+    r = orc.field_range([h[offset:].copy() for h in host])
+    assert (g.view(np.uint32) == r.view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("kind", ["identity", "block", "global", "bad"])
+def test_bound_check_permutations(gpz, orc, kind):
+    """The bound check against the oracle's for identity, block-local, global
+    and invalid permutations, with violations, NaNs and a ragged tail."""
+    rng = np.random.default_rng(11)
+    n, F = 5000, 4
+    orig = [rng.standard_normal(n).astype(np.float32) for _ in range(F)]
+    eb = np.array([1e-3, 1e-2, 1e-4, 1e-3], np.float32)
+    if kind == "identity":
+        perm = None
+    elif kind == "global":
+        perm = rng.permutation(n).astype(np.uint32)
+    else:
+        perm = np.concatenate([1024 * b + rng.permutation(min(1024, n - 1024 * b))
+                               for b in range((n + 1023) // 1024)]).astype(np.uint32)
+        if kind == "bad":
+            perm[[3, 4000]] = [n, 0xFFFFFFFF]
+    src = np.arange(n) if perm is None else np.minimum(perm, n - 1)
+    recon = [(o[src] + rng.uniform(-1.2, 1.2, n).astype(np.float32) * e).astype(np.float32)
+             for o, e in zip(orig, eb)]
+    recon[2][[10, 20]] = np.nan
+    dev_o, dev_r = to_dev(orig), to_dev(recon)
+    dperm = torch.from_numpy(perm.view(np.int32)).cuda() if perm is not None else None
+    viol, mx = gpz.bound_check(dev_o, dev_r, eb, perm=dperm)
+    rviol, rmx = orc.bound_check(orig, recon, eb, perm=perm)
+    assert (viol == rviol).all(), f"{kind}: {viol} vs {rviol}"
+    assert (mx == rmx).all(), f"{kind}: {mx} vs {rmx}"
+    assert viol.sum() > 0
 
 
 def _mini_stream(rec_words, n, F, B, K, KF, eb_bits):
@@ -252,3 +310,46 @@ def test_full_size_cosmology_sampled(gpz, orc, cosmology_full):
     assert (viol == 0).all()
     assert (mx <= eb.astype(np.float64)).all()
     say(f"[case] full cosmology CR {4 * n * F / stream.numel():.3f}")
+
+
+def test_error_stats_parity(gpz, orc):
+    """Rate-distortion figures of a round trip: violations and maximum error
+    exactly; sums of squares (summation order differs: each d*d is exact to
+    within one rounding, so n * 2^-52 relative bounds the difference) and the
+    aggregate PSNR to 1e-9 relative."""
+    from paper_2508_10305_amd import synth
+    host = synth.clusters(200_003, seed=21, extra_fields=2)
+    eb = np.array([1e-4, 1e-3, 1e-2, 1e-3, 1e-4], np.float32)
+    dev = to_dev(host)
+    s, perm = gpz.compress(dev, eb, want_perm=True)
+    out = gpz.decompress(s, host[0].size, len(host))
+    st = gpz.error_stats(dev, out, eb, perm=perm)
+    ref_out = orc.decompress(s.cpu().numpy(), host[0].size, len(host))
+    ref = orc.error_stats(host, ref_out, perm=perm.cpu().numpy().astype(np.uint32))
+    rv, rm = orc.bound_check(host, ref_out, eb, perm=perm.cpu().numpy().astype(np.uint32))
+    assert (st["violations"] == rv).all() and (st["max_abs_err"] == rm).all()
+    assert np.allclose(st["sum_sq"], ref["sum_sq"], rtol=1e-9, atol=0)
+    assert abs(st["psnr"] - ref["psnr"]) <= 1e-9 * abs(ref["psnr"])
+
+
+def test_stream_stats_parity(gpz, orc):
+    """Outlier and raw-block counts of GPU streams equal the oracle's; a
+    broken record length is reported as corrupt."""
+    rng = np.random.default_rng(5)
+    n = 50_000
+    smooth = [np.linspace(0, 1, n).astype(np.float32) for _ in range(3)]
+    for f in range(3):
+        smooth[f][rng.integers(0, n, 40 * (f + 1))] = np.nan
+    noise = [rng.random(n).astype(np.float32) for _ in range(3)]
+    mixed = [np.concatenate([a[: n // 2], b[n // 2:]]) for a, b in zip(smooth, noise)]
+    for label, host, eb in (("smooth", smooth, 1e-3), ("noise", noise, 1e-9), ("mixed", mixed, 1e-7)):
+        s, _ = gpz.compress(to_dev(host), eb)
+        got = gpz.stream_stats(s, n, 3)
+        ref = orc.stream_stats(s.cpu().numpy(), n, 3)
+        say(f"[case] stream stats {label}: {got}")
+        assert got[0].tolist() == ref[0].tolist() and got[1] == ref[1], label
+    bad = s.clone().view(torch.int32)
+    bad[8 + 2 * 1 + 3 + 2] += 1  # length of block 2
+    with pytest.raises(gpz.GpzError) as e:
+        gpz.stream_stats(bad.view(torch.uint8), n, 3)
+    assert e.value.code == gpz.GPZ_ECORRUPT

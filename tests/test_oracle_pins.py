@@ -409,3 +409,48 @@ def test_bound_check_permutation_and_invalid_entries(orc):
     bad[[0, 3]] = [8, 0xFFFFFFFF]
     v, m = orc.bound_check([x], [y], 1e-3, perm=bad)
     assert v.tolist() == [2] and m.tolist() == [0.0]
+
+
+def test_error_stats_closed_form(orc):
+    """Every value off by exactly 0.5 over a range of 100: sum of squares
+    n/4, NRMSE 0.005, aggregate PSNR 20 log10(200) dB (Sec. 2 definition)."""
+    n = 101
+    x = [np.arange(n, dtype=np.float32), np.linspace(-50, 50, n).astype(np.float32)]
+    y = [a + np.float32(0.5) for a in x]
+    st = orc.error_stats(x, y)
+    assert st["sum_sq"].tolist() == [n * 0.25, n * 0.25]
+    assert st["nrmse"].tolist() == [0.005, 0.005]
+    assert abs(st["psnr"] - 20 * np.log10(200.0)) < 1e-12
+    # one exact field and one off by 0.5: mean NRMSE^2 halves (+3.01 dB)
+    st = orc.error_stats(x, [x[0], y[1]])
+    assert abs(st["psnr"] - (20 * np.log10(200.0) + 10 * np.log10(2.0))) < 1e-12
+
+
+def test_error_stats_pairs_like_the_bound_check(orc):
+    """Pairs follow the permutation; NaN differences and entries outside
+    [0, n) are left out of the sum."""
+    x = np.arange(8, dtype=np.float32)
+    y = x[::-1] + np.float32(0.25)
+    perm = np.arange(8, dtype=np.uint32)[::-1].copy()
+    assert orc.error_stats([x], [y], perm=perm)["sum_sq"].tolist() == [8 * 0.0625]
+    y2 = y.copy()
+    y2[2] = np.nan
+    bad = perm.copy()
+    bad[5] = 99
+    assert orc.error_stats([x], [y2], perm=bad)["sum_sq"].tolist() == [6 * 0.0625]
+
+
+def test_stream_stats_counts(orc):
+    """Non-finite values are outliers of coded blocks (one per value);
+    incompressible blocks are raw and count no outliers."""
+    n = 3000
+    smooth = [np.linspace(0, 1, n).astype(np.float32) for _ in range(3)]
+    smooth[1][[5, 1500, 2999]] = [np.nan, np.inf, -np.inf]
+    smooth[2][[7]] = [np.nan]
+    s, _ = orc.compress(smooth, 1e-3)
+    out, raw = orc.stream_stats(s, n, 3)
+    assert out.tolist() == [0, 3, 1] and raw == 0
+    noise = [np.random.default_rng(f).random(n).astype(np.float32) for f in range(3)]
+    s, _ = orc.compress(noise, 1e-9)
+    out, raw = orc.stream_stats(s, n, 3)
+    assert raw == 3 and out.tolist() == [0, 0, 0]
