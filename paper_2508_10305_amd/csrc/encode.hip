@@ -345,14 +345,12 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     const uint32_t cap = 1 + F * nb;  // raw record length
 
     // ---- Stage 1 (Sec. 4.1): key axes -- block minimum, grid index, segment shift
-    // The loads of the key fields and of the first other field are issued
-    // together, so the block waits for memory once rather than once per field.
+    // The loads of the key fields are issued together, so the block waits
+    // for memory once rather than once per key field.
     float xk[3][ITEMS];
 #pragma unroll
     for (int ax = 0; ax < 3; ax++)
         if ((uint32_t)ax < KF) load_block<ITEMS, FULL>(a.x[ax], base, nb, lane, xk[ax]);
-    float xnext[ITEMS];
-    if (KF < F) load_block<ITEMS, FULL>(a.x[KF], base, nb, lane, xnext);
     uint32_t qk[3][ITEMS];
     float lok[3];
     uint32_t sk[3];
@@ -486,11 +484,8 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
                 const uint32_t s = f == 0 ? sk[0] : (f == 1 ? sk[1] : sk[2]);
                 mask = (1u << s) - 1u;
             } else {
-                // this field was loaded one field ahead; start the next one
                 float x[ITEMS];
-#pragma unroll
-                for (int j = 0; j < ITEMS; j++) x[j] = xnext[j];
-                if (f + 1 < F) load_block<ITEMS, FULL>(a.x[f + 1], base, nb, lane, xnext);
+                load_block<ITEMS, FULL>(a.x[f], base, nb, lane, x);
                 lo = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[f], a.twoeb[f], a.eb[f], q);
                 mask = 0xFFFFFFu;
             }
