@@ -661,7 +661,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
     __shared__ EncodeSmem<ITEMS> sm;
     const uint32_t ntail = L->ntail;
     for (uint32_t t = blockIdx.x; t < ntail; t += gridDim.x) {
-        const EncodeArgs& a = jobs[L->tail_jobs[t]];
+        const EncodeArgs& a = jobs[__builtin_amdgcn_readfirstlane((int)L->tail_jobs[t])];
         const uint32_t b = a.nblocks - 1;
         const uint32_t nb = (uint32_t)(a.n - (uint64_t)b * B);
         encode_block<ITEMS, false, false>(a, b, nb, sm.kvbuf, sm.work);

@@ -212,6 +212,8 @@ hipError_t launch_field_range(const float* const* x, uint64_t n, uint32_t F, int
 // block g of the flattened list belongs to the job j with
 // prefix[j] <= g < prefix[j+1] (found by a uniform binary search).
 
+// g must be wave-uniform; the result is returned through readfirstlane so
+// the compiler keeps it (and the job arguments it indexes) in scalar registers.
 __device__ __forceinline__ uint32_t find_job(const uint32_t* __restrict__ prefix, uint32_t njobs,
                                              uint32_t g) {
     uint32_t lo = 0, hi = njobs;
@@ -220,7 +222,7 @@ __device__ __forceinline__ uint32_t find_job(const uint32_t* __restrict__ prefix
         if (prefix[mid] <= g) lo = mid;
         else hi = mid;
     }
-    return lo;
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
 }
 
 // Launch descriptor of a batch, kept in device memory so that a captured

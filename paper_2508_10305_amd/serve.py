@@ -123,8 +123,12 @@ class Server:
 
     def __init__(self, budget_bytes: int, nstreams: int = 3, max_jobs: int = 64,
                  max_blocks: int = 1 << 20, p: Optional[Params] = None, config=None,
-                 device="cuda"):
+                 device="cuda", batch_below_blocks: int = 1024):
+        """`batch_below_blocks`: requests of at most this many blocks are
+        batched together; larger ones fill the GPU on their own and get a
+        plain launch."""
         import torch
+        self.batch_below_blocks = batch_below_blocks
         self.p = p if p is not None else params(3)
         self.B = self.p.block_size
         self.arena = Arena(budget_bytes, device)
@@ -247,8 +251,23 @@ class Server:
         batching) or "per_request".  `on_done(request)` is called when a
         request's result is complete, before its buffers are released.
         Returns latency and throughput stats."""
+        import gc
+
         import torch
         torch.cuda.synchronize()
+        # a full garbage collection in the middle of the loop stalls every
+        # request in flight (tens of ms); collect before, not during
+        gc.collect()
+        gc_was_on = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, mode, time_scale, max_batch, on_done, stall_timeout)
+        finally:
+            if gc_was_on:
+                gc.enable()
+
+    def _run(self, requests, mode, time_scale, max_batch, on_done, stall_timeout) -> Dict:
+        import torch
         max_batch = max_batch or self.max_jobs
         pending = list(requests)
         waiting: List[Request] = []
@@ -279,10 +298,8 @@ class Server:
             while i < len(pending) and pending[i].t * time_scale <= now:
                 r = pending[i]
                 i += 1
-                nb = (r.n + self.B - 1) // self.B
-                if self._request_bytes(r) > self.arena.size or (
-                        mode == "batched" and nb > self.max_blocks):
-                    rejected.append(r)  # can never fit the budget or a batch
+                if self._request_bytes(r) > self.arena.size:
+                    rejected.append(r)  # can never fit the budget
                 else:
                     waiting.append(r)
                 last_progress = now
@@ -301,15 +318,28 @@ class Server:
                         admitted.pop(0)
                         last_progress = now
                 else:
+                    small = lambda r: (r.n + self.B - 1) // self.B <= self.batch_below_blocks
                     take, blocks = [], 0
-                    for r in admitted:
-                        nb = (r.n + self.B - 1) // self.B
-                        if len(take) >= max_batch or blocks + nb > self.max_blocks:
-                            break
-                        take.append(r)
-                        blocks += nb
-                    if take and self._launch(slot, take):
-                        del admitted[: len(take)]
+                    if small(admitted[0]):
+                        # the small admitted requests, in arrival order
+                        for r in admitted:
+                            if not small(r):
+                                continue
+                            nb = (r.n + self.B - 1) // self.B
+                            if len(take) >= max_batch or blocks + nb > self.max_blocks:
+                                break
+                            take.append(r)
+                            blocks += nb
+                    # a large request, or a lone small one, gets a plain launch
+                    # (rebinding a batch costs more than a batch of one saves)
+                    if len(take) <= 1:
+                        r = admitted[0]
+                        if self._launch_single(slot, r):
+                            admitted.pop(0)
+                            last_progress = now
+                    elif self._launch(slot, take):
+                        ids = set(id(r) for r in take)
+                        admitted[:] = [r for r in admitted if id(r) not in ids]
                         last_progress = now
         wall = time.perf_counter() - t0
         lat = np.array([r.t_done - r.t * time_scale for r in done]) * 1e3

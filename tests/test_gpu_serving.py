@@ -67,7 +67,7 @@ def test_each_result_same_alone_and_in_the_mix(setup, mode):
     check_same(gpz, rs, results)
     assert st["requests"] == len(reqs)
     if mode == "batched":
-        assert st["mean_batch"] >= 1.0
+        assert max(srv.batch_sizes) > 1, "no request was batched with another"
     srv.close()
 
 
