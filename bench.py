@@ -70,7 +70,8 @@ def main():
                     help="plain per-snapshot launch (default), batched snapshots, serving loop, "
                          "or a plain device copy of the snapshot's bytes (HBM reference)")
     ap.add_argument("--batch-grid", type=int, default=0,
-                    help="batched form: persistent grid (skips the autotuner with --batch-tile)")
+                    help="batched form: persistent grid, 0 = one workgroup per block (with "
+                         "--batch-tile, skips the autotuner)")
     ap.add_argument("--batch-tile", type=int, default=0)
     ap.add_argument("--jobs", type=int, default=256, help="snapshots of the batched form")
     ap.add_argument("--requests", type=int, default=20_000, help="requests of the serving form")
@@ -360,7 +361,7 @@ def bench_batched(args):
 
     total_blocks = sum((sp["n"] + 1023) // 1024 for sp in specs)
     key = autotune.shape_key(torch.cuda.get_device_name(0), 1024, total_blocks, len(specs))
-    if args.batch_grid and args.batch_tile:
+    if args.batch_tile:  # fixed launch shape (grid 0: one workgroup per block)
         tuned = {"grid": args.batch_grid, "tile": args.batch_tile, "table": []}
     else:
         tuned = autotune.tune(run, cus, key, use_cache=False, log=log)

@@ -206,7 +206,8 @@ typedef struct {
 } gpz_job;
 
 typedef struct {
-    uint32_t grid;       /* persistent workgroups (one wave each); default 8 per CU */
+    uint32_t grid;       /* persistent workgroups (one wave each); default 8 per CU;
+                            0: one workgroup per block of the capacity instead */
     uint32_t tile;       /* consecutive blocks taken per work-queue grab; default 1 */
     uint32_t use_graph;  /* 1: capture the kernel sequence once, then replay it */
     uint32_t max_jobs;   /* capacity for gpz_batch_rebind (0: the creation job count) */

@@ -51,12 +51,14 @@ def tune(run: Callable[[int, int], float], cus: int, key: str, reps: int = 1,
     if use_cache and key in cache:
         return cache[key]
     table = []
-    for g in GRID_PER_CU:
-        for t in TILES:
-            ms = min(run(g * cus, t) for _ in range(reps))
-            table.append({"grid": g * cus, "tile": t, "ms": ms})
-            if log:
-                log(f"[tune] grid={g * cus} tile={t}: {ms:.3f} ms")
+    # persistent grids of 2..16 workgroups per CU x tile, and grid 0: one
+    # workgroup per block (no persistent loop)
+    shapes = [(g * cus, t) for g in GRID_PER_CU for t in TILES] + [(0, 1)]
+    for grid, t in shapes:
+        ms = min(run(grid, t) for _ in range(reps))
+        table.append({"grid": grid, "tile": t, "ms": ms})
+        if log:
+            log(f"[tune] grid={grid} tile={t}: {ms:.3f} ms")
     best = min(table, key=lambda r: r["ms"])
     rec = {"grid": best["grid"], "tile": best["tile"], "ms": best["ms"], "table": table}
     cache[key] = rec

@@ -313,7 +313,7 @@ int gpz_batch_create(gpz_batch** out, const gpz_job* jobs, uint32_t njobs, const
     gpz_batch_config c;
     gpz_default_batch_config(&c);
     if (cfg) c = *cfg;
-    if (c.grid == 0 || c.tile == 0) return GPZ_EINVAL;
+    if (c.tile == 0) return GPZ_EINVAL;
     const uint32_t B = p.block_size;
     uint64_t nblocks_all = 0, nsuper_all = 0;
     for (uint32_t j = 0; j < njobs; j++) {
@@ -334,9 +334,10 @@ int gpz_batch_create(gpz_batch** out, const gpz_job* jobs, uint32_t njobs, const
     }
     b->shape.B = B;
     b->shape.grid = c.grid;
+    b->shape.direct_grid = (uint32_t)(b->max_blocks ? b->max_blocks : 1);
     b->shape.scan_grid = b->max_jobs < 256 ? b->max_jobs : 256;
-    b->shape.copy_grid = c.grid;  // 4-wave workgroups: 4 x grid waves copying
-    b->shape.tail_grid = b->max_jobs < 64 ? b->max_jobs : 64;
+    b->shape.copy_grid = c.grid ? c.grid : 2048;  // 4-wave workgroups copying
+    b->shape.tail_grid = b->max_jobs < 1024 ? b->max_jobs : 1024;  // every tail at once
     const uint32_t mj = b->max_jobs;
     const uint64_t mb = b->max_blocks, ms = b->max_super;
     uint64_t o = 0;

@@ -349,17 +349,42 @@ __global__ __launch_bounds__(64) void decode_batch(const DecodeArgs* __restrict_
     }
 }
 
+// Direct form of decode_batch: one workgroup per block of the batch's
+// capacity (no loop around the block, so a smaller register budget).
+template <int ITEMS>
+__global__ __launch_bounds__(64) void decode_batch_direct(const DecodeArgs* __restrict__ jobs,
+                                                          const BatchLaunch* __restrict__ L) {
+    __shared__ __align__(16) DecodeSmem<ITEMS> sm;
+    const uint32_t g = blockIdx.x;
+    if (g >= L->total_blocks) return;
+    const uint32_t* prefix = L->block_prefix;
+    const uint32_t j = find_job(prefix, L->njobs, g);
+    decode_block<ITEMS>(jobs[j], g - prefix[j], sm);
+}
+
 }  // namespace
 
 hipError_t launch_decode_batch(const DecodeArgs* jobs, const BatchLaunch* L,
                                const BatchShape& S, hipStream_t s) {
-    dim3 grid(S.grid), block(64);
-    switch (S.B) {
-        case 256: hipLaunchKernelGGL(decode_batch<4>, grid, block, 0, s, jobs, L); break;
-        case 512: hipLaunchKernelGGL(decode_batch<8>, grid, block, 0, s, jobs, L); break;
-        case 1024: hipLaunchKernelGGL(decode_batch<16>, grid, block, 0, s, jobs, L); break;
-        case 2048: hipLaunchKernelGGL(decode_batch<32>, grid, block, 0, s, jobs, L); break;
-        default: return hipErrorInvalidValue;
+    dim3 block(64);
+    if (S.grid) {
+        dim3 grid(S.grid);
+        switch (S.B) {
+            case 256: hipLaunchKernelGGL(decode_batch<4>, grid, block, 0, s, jobs, L); break;
+            case 512: hipLaunchKernelGGL(decode_batch<8>, grid, block, 0, s, jobs, L); break;
+            case 1024: hipLaunchKernelGGL(decode_batch<16>, grid, block, 0, s, jobs, L); break;
+            case 2048: hipLaunchKernelGGL(decode_batch<32>, grid, block, 0, s, jobs, L); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        dim3 grid(S.direct_grid);
+        switch (S.B) {
+            case 256: hipLaunchKernelGGL(decode_batch_direct<4>, grid, block, 0, s, jobs, L); break;
+            case 512: hipLaunchKernelGGL(decode_batch_direct<8>, grid, block, 0, s, jobs, L); break;
+            case 1024: hipLaunchKernelGGL(decode_batch_direct<16>, grid, block, 0, s, jobs, L); break;
+            case 2048: hipLaunchKernelGGL(decode_batch_direct<32>, grid, block, 0, s, jobs, L); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }

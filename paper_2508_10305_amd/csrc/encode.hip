@@ -653,6 +653,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
     }
 }
 
+// Direct form of encode_batch: one workgroup per full block of the batch's
+// capacity; workgroups past the bound jobs' blocks exit at once.  No loop
+// around the block, so the compiler keeps the register budget of the plain
+// kernel.
+template <int ITEMS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_batch_direct(
+    const EncodeArgs* __restrict__ jobs, const BatchLaunch* __restrict__ L) {
+    constexpr uint32_t B = 64 * ITEMS;
+    __shared__ EncodeSmem<ITEMS> sm;
+    const uint32_t g = blockIdx.x;
+    if (g >= L->total_full) return;
+    const uint32_t* prefix = L->full_prefix;
+    const uint32_t j = find_job(prefix, L->njobs, g);
+    encode_block<ITEMS, true, false>(jobs[j], g - prefix[j], B, sm.kvbuf, sm.work);
+}
+
 // The partial last block of each snapshot that has one.
 template <int ITEMS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_batch_tails(const EncodeArgs* __restrict__ jobs,
@@ -672,7 +688,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
 template <int ITEMS>
 void launch_encode_batch_items(const EncodeArgs* jobs, const BatchLaunch* L, const BatchShape& S,
                                hipStream_t s) {
-    hipLaunchKernelGGL(encode_batch<ITEMS>, dim3(S.grid), dim3(64), 0, s, jobs, L);
+    if (S.grid) hipLaunchKernelGGL(encode_batch<ITEMS>, dim3(S.grid), dim3(64), 0, s, jobs, L);
+    else hipLaunchKernelGGL(encode_batch_direct<ITEMS>, dim3(S.direct_grid), dim3(64), 0, s, jobs, L);
     hipLaunchKernelGGL(encode_batch_tails<ITEMS>, dim3(S.tail_grid), dim3(64), 0, s, jobs, L);
 }
 

@@ -243,7 +243,9 @@ struct BatchLaunch {
 // Launch shapes of the batched kernels (fixed for the life of a batch).
 struct BatchShape {
     uint32_t B;
-    uint32_t grid;        // persistent encode / decode workgroups (one wave each)
+    uint32_t grid;        // persistent encode / decode workgroups (one wave each);
+                          // 0: one workgroup per block instead (direct_grid of them)
+    uint32_t direct_grid; // block capacity of the batch (direct launches)
     uint32_t scan_grid;   // workgroups striding over jobs for the scans
     uint32_t copy_grid;   // 4-wave workgroups striding over blocks for the copies
     uint32_t tail_grid;   // workgroups striding over the partial tail blocks

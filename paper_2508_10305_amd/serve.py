@@ -459,7 +459,8 @@ def bench_main(args, log=print):
                                 ("per_request", 200 << 30, "per_request"),
                                 ("batched_overload", 8 << 30, "batched"),
                                 ("per_request_overload", 8 << 30, "per_request")):
-        budget = min(budget, int(torch.cuda.mem_get_info()[0] * 0.6))
+        # the budget, less 16 GB kept free for the batches' tables and torch
+        budget = min(budget, int(torch.cuda.mem_get_info()[0]) - (16 << 30))
         srv = Server(budget, nstreams=3, max_jobs=64, max_blocks=1 << 20)
         rate_scale = 1.0 if "overload" not in label else 0.1  # 10x arrival rate
         st = srv.run(fresh(reqs), mode=mode, time_scale=rate_scale)
@@ -467,6 +468,8 @@ def bench_main(args, log=print):
         st["arrival_rate_per_s"] = 2000.0 / rate_scale
         results[label] = st
         srv.close()
+        del srv  # hand the arena back before the next run sizes its own
+        torch.cuda.empty_cache()
         log(f"[serve] {label}: p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms "
             f"{st['sustained_GBps']:.1f} GB/s, {st['batches']} launches")
         torch.cuda.synchronize()

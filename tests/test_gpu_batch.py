@@ -76,8 +76,10 @@ def check_batch(b, outs, decs, ref, label):
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
-@pytest.mark.parametrize("tile", [1, 3])
-def test_batch_equals_plain(gpz, use_graph, tile):
+@pytest.mark.parametrize("grid,tile", [(97, 1), (97, 3), (0, 1)])
+def test_batch_equals_plain(gpz, use_graph, grid, tile):
+    """grid 97: an odd persistent grid, blocks shared unevenly between waves;
+    grid 0: one workgroup per block."""
     from paper_2508_10305_amd.batch import default_config
     sizes = [1, 1023, 1024, 1025, 5000, 0, 70_000, 200_001, 64 * 1024 + 7, 3]
     jobs = make_jobs(7, sizes)
@@ -85,12 +87,12 @@ def test_batch_equals_plain(gpz, use_graph, tile):
     cfg = default_config()
     cfg.use_graph = use_graph
     cfg.tile = tile
-    cfg.grid = 97  # odd persistent grid: blocks are shared unevenly between waves
-    say(f"[case] batch graph={use_graph} tile={tile}")
+    cfg.grid = grid
+    say(f"[case] batch graph={use_graph} grid={grid} tile={tile}")
     b, fields, outs, decs, ebs = build_batch(gpz, jobs, cfg)
     b.compress()
     b.decompress()
-    check_batch(b, outs, decs, ref, f"graph={use_graph} tile={tile}")
+    check_batch(b, outs, decs, ref, f"graph={use_graph} grid={grid} tile={tile}")
     b.close()
 
 
@@ -127,12 +129,17 @@ def test_graph_replays_with_eager_work_between(gpz):
     b.close()
 
 
-def test_rebind_keeps_graphs_valid(gpz):
+@pytest.mark.parametrize("grid", [2048, 0])
+def test_rebind_keeps_graphs_valid(gpz, grid):
+    from paper_2508_10305_amd.batch import default_config
     jobs_a = make_jobs(17, [30_000, 2_000, 9_000])
     jobs_b = make_jobs(19, [100_000, 1_500])
     ref_b = plain_results(gpz, jobs_b)
     total_blocks = sum((h[0].size + 1023) // 1024 for h, _ in jobs_a + jobs_b)
-    b, *_ = build_batch(gpz, jobs_a, max_jobs=8, max_blocks=total_blocks)
+    cfg = default_config()
+    cfg.grid = grid
+    # the capacity exceeds both job lists: direct launches exit past them
+    b, *_ = build_batch(gpz, jobs_a, cfg, max_jobs=8, max_blocks=total_blocks + 37)
     b.compress()
     b.decompress()
     torch.cuda.synchronize()
@@ -145,7 +152,7 @@ def test_rebind_keeps_graphs_valid(gpz):
         decs.append([torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(F)])
         ebs.append(eb)
     ws = torch.empty(b.workspace_bytes(fields, ebs, outs, decs), dtype=torch.uint8, device="cuda")
-    say("[case] rebind")
+    say(f"[case] rebind grid={grid}")
     b.rebind(fields, ebs, outs, dec=decs, workspace=ws)
     b.compress()
     b.decompress()
