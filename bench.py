@@ -66,9 +66,11 @@ def main():
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--cpu-sample-blocks", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["plain", "batched", "serving", "copy"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batched", "serving", "copy", "rd"],
+                    default="plain",
                     help="plain per-snapshot launch (default), batched snapshots, serving loop, "
-                         "or a plain device copy of the snapshot's bytes (HBM reference)")
+                         "a plain device copy of the snapshot's bytes (HBM reference), or a "
+                         "rate-distortion sweep over the synthetic workloads")
     ap.add_argument("--batch-grid", type=int, default=0,
                     help="batched form: persistent grid, 0 = one workgroup per block (with "
                          "--batch-tile, skips the autotuner)")
@@ -90,6 +92,8 @@ def main():
         return serve.bench_main(args, log=log)
     if args.form == "copy":
         return bench_copy(args)
+    if args.form == "rd":
+        return bench_rd(args)
 
     import torch
 
@@ -211,7 +215,7 @@ def main():
         "single_pass_kernels_ms": {k: round(avg1[k], 4) for k in ("prepare", "encode")},
     }
 
-    cpu = None
+    cpu = cpu_parallel = None
     if not args.no_cpu_baseline:
         import oracle
         m = min(n, args.cpu_sample_blocks * p.block_size)
@@ -226,6 +230,25 @@ def main():
                "sample": f"first {m} particles ({m // p.block_size} blocks) x {F} fields of the "
                          f"snapshot; compress {t1 - t0:.2f}s + decompress {t2 - t1:.2f}s, "
                          f"single-threaded C"}
+        # the same sample split into block-aligned chunks, one oracle call per
+        # host thread (blocks are independent; ctypes releases the GIL)
+        from concurrent.futures import ThreadPoolExecutor
+        T = max(1, min(16, len(os.sched_getaffinity(0))))
+        cb = (m // p.block_size + T - 1) // T * p.block_size
+        chunks = [(lo, min(m, lo + cb)) for lo in range(0, m, cb)]
+
+        def one(c):
+            part = [np.ascontiguousarray(f[c[0]:c[1]]) for f in sample]
+            s_, _ = oracle.compress(part, eb)
+            oracle.decompress(s_, c[1] - c[0], F)
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(len(chunks)) as ex:
+            list(ex.map(one, chunks))
+        t3 = time.perf_counter()
+        cpu_parallel = {"value": round(2 * 4 * m * F / (t3 - t0) / 1e9, 5), "unit": "GB/s",
+                        "cores": len(chunks), "kind": "oracle",
+                        "sample": f"the same {m} particles in {len(chunks)} block-aligned chunks, "
+                                  f"one oracle compress + decompress per thread, {t3 - t0:.2f}s"}
 
     lat.sort()
     rec = {
@@ -247,6 +270,7 @@ def main():
                    "rel_eb": args.rel},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_parallel": cpu_parallel,
         "compress_GBps": round(S / (t_c * 1e-3) / 1e9, 2),
         "decompress_GBps": round(S / (t_d * 1e-3) / 1e9, 2),
         "compression_ratio": round(S / C, 4),
@@ -262,6 +286,67 @@ def main():
                              "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3)},
     }
     print(json.dumps(rec), flush=True)
+
+
+def bench_rd(args):
+    """Rate-distortion sweep (Sec. 2's analysis: bit rate against aggregate
+    PSNR) over the four synthetic workloads at their full sizes and relative
+    bounds 1e-2 ... 1e-5, with compression ratio, outliers and GPU rates."""
+    import torch
+
+    import paper_2508_10305_amd as gpz
+    from paper_2508_10305_amd import synth
+    workloads = (("cosmology", 64_000_000), ("md", 32_000_000), ("lidar", 100_000_000),
+                 ("clusters", 1_000_000))
+    rels = (1e-2, 1e-3, 1e-4, 1e-5)
+    rows = []
+    for kind, n in workloads:
+        t0 = time.time()
+        host = synth.make(kind, n, {"clusters": 0, "cosmology": 1, "md": 2, "lidar": 3}[kind])
+        fields = [torch.from_numpy(f).cuda() for f in host]
+        del host
+        n, F = fields[0].numel(), len(fields)
+        S = 4 * n * F
+        log(f"[rd] {kind}: {n} x {F} generated in {time.time() - t0:.1f}s")
+        p = gpz.params(F)
+        comp = gpz.Compressor(n, F, p)
+        outs = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(F)]
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for rel in rels:
+            eb = gpz.rel_ebs(fields, rel)
+            stream, perm = comp.compress(fields, eb, want_perm=True)
+            C = int(stream.numel())
+            gpz.decompress(stream, n, F, out=outs)
+            st = gpz.error_stats(fields, outs, eb, perm=perm)
+            outl, raw_blocks = gpz.stream_stats(stream, n, F)
+            assert int(st["violations"].sum()) == 0
+            del perm
+            reps = 5
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            for _ in range(reps):
+                comp.compress_async(fields, eb)
+            e[1].record()
+            for _ in range(reps):
+                gpz.decompress_async(comp.out, n, F, outs, err, p)
+            e[2].record()
+            torch.cuda.synchronize()
+            tc, td = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+            row = {"workload": kind, "n": n, "fields": F, "rel_eb": rel,
+                   "compression_ratio": round(S / C, 3),
+                   "bit_rate_bits_per_value": round(8 * C / (n * F), 4),
+                   "aggregate_psnr_db": round(st["psnr"], 3),
+                   "nrmse": [float(f"{v:.4g}") for v in st["nrmse"]],
+                   "outlier_fraction": float(outl.sum()) / (n * F), "raw_blocks": raw_blocks,
+                   "compress_GBps": round(S / (tc * 1e-3) / 1e9, 1),
+                   "decompress_GBps": round(S / (td * 1e-3) / 1e9, 1)}
+            rows.append(row)
+            log(f"[rd] {kind} rel {rel:g}: CR {row['compression_ratio']} "
+                f"{row['bit_rate_bits_per_value']} bits/value PSNR {row['aggregate_psnr_db']} dB")
+        del comp, fields, outs
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "rate-distortion: bit rate vs aggregate PSNR", "form": "rd",
+                      "data": "synthetic", "rows": rows}), flush=True)
 
 
 def bench_copy(args):

@@ -92,3 +92,43 @@ def test_invalid_arguments_rejected_before_device_work(gpz):
 def test_strerror(gpz):
     for c in range(-6, 1):
         assert gpz.lib().gpz_strerror(c)
+
+
+def test_batch_and_stats_entry_points_reject_bad_arguments(gpz):
+    """Host-side argument checks of the batch, statistics and timing entry
+    points: every one returns a status before touching the device."""
+    L = gpz.lib()
+    assert L.gpz_batch_destroy(None) == gpz.GPZ_OK
+    assert L.gpz_batch_compress(None, None) == gpz.GPZ_EINVAL
+    assert L.gpz_batch_decompress(None, None) == gpz.GPZ_EINVAL
+    assert L.gpz_batch_sizes(None) is None and L.gpz_batch_errors(None) is None
+    jobs = (gpz.Job * 1)()  # zeroed job: no fields, no eb, no output
+    assert L.gpz_batch_workspace_bytes(jobs, 1, None) == 0
+    b = ctypes.c_void_p()
+    p = gpz.Params()
+    L.gpz_default_params(ctypes.byref(p), 3)
+    p.block_size = 100  # not a power of two
+    assert L.gpz_batch_create(ctypes.byref(b), jobs, 1, ctypes.byref(p), None, None, 0) == \
+        gpz.GPZ_EINVAL
+    assert L.gpz_batch_create(None, jobs, 1, None, None, None, 0) == gpz.GPZ_EINVAL
+    assert L.gpz_error_stats(None, None, None, 10, 0, None, None, None, None, None) == \
+        gpz.GPZ_EINVAL
+    assert L.gpz_stream_stats(None, 100, 10, 3, None, None, None) == gpz.GPZ_EINVAL
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_uint32 * 5)()
+    assert L.gpz_timing_collect(None, cnt, 5) == gpz.GPZ_EINVAL
+    assert L.gpz_timing_collect(ms, cnt, 0) == gpz.GPZ_EINVAL
+
+
+def test_flags_select_compaction_only(gpz):
+    """Only GPZ_FLAG_SINGLE_PASS is a valid flag; it does not change sizes."""
+    L = gpz.lib()
+    p = gpz.params(3)
+    base = L.gpz_compress_workspace_bytes(100_000, 3, ctypes.byref(p))
+    p1 = gpz.params(3, single_pass=True)
+    assert p1.flags == gpz.GPZ_FLAG_SINGLE_PASS
+    assert L.gpz_compress_workspace_bytes(100_000, 3, ctypes.byref(p1)) == base > 0
+    assert L.gpz_max_compressed_bytes(100_000, 3, ctypes.byref(p1)) == \
+        L.gpz_max_compressed_bytes(100_000, 3, ctypes.byref(p))
+    p.flags = 2
+    assert L.gpz_compress_workspace_bytes(100_000, 3, ctypes.byref(p)) == 0

@@ -353,3 +353,26 @@ def test_stream_stats_parity(gpz, orc):
     with pytest.raises(gpz.GpzError) as e:
         gpz.stream_stats(bad.view(torch.uint8), n, 3)
     assert e.value.code == gpz.GPZ_ECORRUPT
+
+
+@pytest.mark.parametrize("single_pass", [False, True])
+def test_kernel_timing_log(gpz, single_pass):
+    """The event log records one entry per kernel of each call: clearing,
+    encoder, scan and copy (three-step) or clearing and encoder (single
+    pass), and the decoder."""
+    from paper_2508_10305_amd import synth
+    host = synth.clusters(300_000, seed=4)
+    dev = to_dev(host)
+    gpz.set_timing(True)
+    gpz.timing_collect()
+    s, _ = gpz.compress(dev, 1e-4, single_pass=single_pass)
+    s, _ = gpz.compress(dev, 1e-4, single_pass=single_pass)
+    gpz.decompress(s, 300_000, 3)
+    kt = gpz.timing_collect()
+    gpz.set_timing(False)
+    counts = {k: v[1] for k, v in kt.items()}
+    want = {"prepare": 2, "encode": 2, "decode": 1, "scan": 0 if single_pass else 2,
+            "copy": 0 if single_pass else 2}
+    assert counts == want, counts
+    assert all(kt[k][0] > 0 for k in want if want[k])
+    assert gpz.timing_collect()["encode"][1] == 0  # the log was cleared
