@@ -345,12 +345,17 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     const uint32_t cap = 1 + F * nb;  // raw record length
 
     // ---- Stage 1 (Sec. 4.1): key axes -- block minimum, grid index, segment shift
-    // The loads of the key fields are issued together, so the block waits
-    // for memory once rather than once per key field.
-    float xk[3][ITEMS];
+    // The loads of the key fields and of up to three other fields are all
+    // issued here, before any store of the block: vector memory operations
+    // complete in issue order, so a load issued behind the record's stores
+    // would wait for them.
+    float xk[3][ITEMS], xo[3][ITEMS];
 #pragma unroll
     for (int ax = 0; ax < 3; ax++)
         if ((uint32_t)ax < KF) load_block<ITEMS, FULL>(a.x[ax], base, nb, lane, xk[ax]);
+#pragma unroll
+    for (int e = 0; e < 3; e++)
+        if (KF + e < F) load_block<ITEMS, FULL>(a.x[KF + e], base, nb, lane, xo[e]);
     uint32_t qk[3][ITEMS];
     float lok[3];
     uint32_t sk[3];
@@ -369,6 +374,21 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         } else {
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) qk[ax][j] = 0;
+        }
+    }
+    // the other early fields: grid index and outlier flag (Sec. 4.1)
+    uint32_t qo[3][ITEMS];
+    float loo[3];
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+        loo[e] = 0.0f;
+        if (KF + e < F) {
+            const uint32_t f = KF + e;
+            loo[e] = quantize_field<ITEMS, FULL>(xo[e], nb, lane, a.inv[f], a.twoeb[f], a.eb[f],
+                                                 qo[e]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) qo[e][j] = 0;
         }
     }
 
@@ -483,6 +503,13 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
                 lo = f == 0 ? lok[0] : (f == 1 ? lok[1] : lok[2]);
                 const uint32_t s = f == 0 ? sk[0] : (f == 1 ? sk[1] : sk[2]);
                 mask = (1u << s) - 1u;
+            } else if (f - KF < 3) {
+                const uint32_t e = f - KF;
+#pragma unroll
+                for (int j = 0; j < ITEMS; j++)
+                    q[j] = e == 0 ? qo[0][j] : (e == 1 ? qo[1][j] : qo[2][j]);
+                lo = e == 0 ? loo[0] : (e == 1 ? loo[1] : loo[2]);
+                mask = 0xFFFFFFu;
             } else {
                 float x[ITEMS];
                 load_block<ITEMS, FULL>(a.x[f], base, nb, lane, x);
