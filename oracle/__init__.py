@@ -41,6 +41,22 @@ def build_oracle() -> str:
     return LIB
 
 
+FUZZ_SRC = os.path.join(HERE, "fuzz_decode.c")
+FUZZ_BIN = os.path.join(os.path.dirname(LIB), "fuzz_decode")
+
+
+def build_fuzz_driver() -> str:
+    """Compile the stream-reader robustness driver with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only)."""
+    os.makedirs(os.path.dirname(FUZZ_BIN), exist_ok=True)
+    tmp = FUZZ_BIN + ".tmp"
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-o", tmp, SRC, FUZZ_SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, FUZZ_BIN)
+    return FUZZ_BIN
+
+
 _lib = None
 
 

@@ -132,3 +132,19 @@ def test_flags_select_compaction_only(gpz):
         L.gpz_max_compressed_bytes(100_000, 3, ctypes.byref(p))
     p.flags = 2
     assert L.gpz_compress_workspace_bytes(100_000, 3, ctypes.byref(p)) == 0
+
+
+def test_injected_allocation_failure(gpz, monkeypatch):
+    """With no caller workspace the library allocates one; an injected
+    allocation failure (GPZ_FAULT=alloc) surfaces as GPZ_ENOMEM before any
+    device work."""
+    L = gpz.lib()
+    monkeypatch.setenv("GPZ_FAULT", "alloc")
+    p = gpz.params(3)
+    fake = (ctypes.c_void_p * 3)(0x1000, 0x2000, 0x3000)  # never dereferenced on the host
+    ebs = np.full(3, 1e-3, np.float32)
+    nbytes = ctypes.c_uint64(0)
+    rc = L.gpz_compress(ctypes.cast(fake, ctypes.c_void_p), 5000, 3,
+                        ebs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), 0x4000, 1 << 20,
+                        ctypes.byref(nbytes), None, None, 0, None)
+    assert rc == gpz.GPZ_ENOMEM

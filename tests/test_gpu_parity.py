@@ -376,3 +376,25 @@ def test_kernel_timing_log(gpz, single_pass):
     assert counts == want, counts
     assert all(kt[k][0] > 0 for k in want if want[k])
     assert gpz.timing_collect()["encode"][1] == 0  # the log was cleared
+
+
+def test_random_parameters_match_oracle(gpz, orc):
+    """Random block sizes, segment bits, key-field counts, bounds and value
+    mixes (the property-test generator of the oracle): GPU stream, permutation
+    and decompressed bits equal the oracle's in every case."""
+    from hypothesis import HealthCheck, given, settings
+    from hypothesis import strategies as st
+    from test_oracle_properties import KINDS, make_fields
+
+    @settings(max_examples=40, deadline=None, derandomize=True,
+              suppress_health_check=[HealthCheck.too_slow])
+    @given(B=st.sampled_from([256, 512, 1024, 2048]), n=st.integers(1, 9000),
+           F=st.integers(1, 8), K=st.integers(0, 5), kf=st.integers(1, 3),
+           e=st.floats(-6.0, -1.0), seed=st.integers(0, 2**32 - 1), kind=st.sampled_from(KINDS))
+    def one(B, n, F, K, kf, e, seed, kind):
+        KF = min(kf, F)
+        eb = float(np.float32(10.0 ** e))
+        host = make_fields(n, F, eb, seed, kind)
+        check_case(gpz, orc, host, eb, B=B, K=K, KF=KF, label=f"random {kind}")
+
+    one()
