@@ -55,7 +55,8 @@ def build_batch(gpz, jobs, config=None, **kw):
     for host, eb in jobs:
         n, F = host[0].size, len(host)
         fields.append([torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in host])
-        outs.append(torch.zeros(gpz.max_compressed_bytes(n, F), dtype=torch.uint8, device="cuda"))
+        outs.append(torch.zeros(gpz.max_compressed_bytes(n, F, kw.get("p")), dtype=torch.uint8,
+                                device="cuda"))
         decs.append([torch.full((max(n, 1),), np.nan, dtype=torch.float32, device="cuda")[:n]
                      for _ in range(F)])
         ebs.append(eb)
@@ -173,4 +174,30 @@ def test_batch_reports_corrupt_stream(gpz):
     b.decompress()
     err = b.errors()
     assert err[0] == 0 and err[1] != 0
+    b.close()
+
+
+@pytest.mark.parametrize("B", [256, 2048])
+@pytest.mark.parametrize("grid", [300, 0])
+def test_batch_other_block_sizes(gpz, B, grid):
+    """Batched streams equal plain ones at other block sizes too (full and
+    partial blocks, persistent and direct launches)."""
+    from paper_2508_10305_amd.batch import default_config
+    jobs = make_jobs(29 + B, [B - 1, B, 3 * B + 5, 40_000, 0, 7])
+    p = gpz.params(3, block_size=B)
+    ref = []
+    for host, eb in jobs:
+        n = host[0].size
+        dev = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in host]
+        pp = gpz.params(len(host), block_size=B)
+        s, _ = gpz.compress(dev, eb, block_size=B, key_fields=pp.key_fields)
+        out = gpz.decompress(s, n, len(host))
+        ref.append((s.cpu().numpy(), [o.cpu().numpy() for o in out]))
+    cfg = default_config()
+    cfg.grid = grid
+    say(f"[case] batch B={B} grid={grid}")
+    b, fields, outs, decs, ebs = build_batch(gpz, jobs, cfg, p=p)
+    b.compress()
+    b.decompress()
+    check_batch(b, outs, decs, ref, f"B={B} grid={grid}")
     b.close()
