@@ -247,8 +247,15 @@ int gpz_batch_compress(gpz_batch *b, void *stream);
  * gpz_batch_errors(b)[job] (device uint32) nonzero. */
 int gpz_batch_decompress(gpz_batch *b, void *stream);
 
+/* Device arrays owned by the batch, one entry per bound job: stream sizes in
+ * bytes (written by gpz_batch_compress) and decode error flags (written by
+ * gpz_batch_decompress).  Valid until gpz_batch_destroy; NULL for b == NULL. */
 const uint64_t *gpz_batch_sizes(const gpz_batch *b);
 const uint32_t *gpz_batch_errors(const gpz_batch *b);
+
+/* Releases the batch (graphs, tables, its capture stream).  Waits for the
+ * device first, so a launch still queued on any stream is not left with
+ * freed tables.  NULL is a no-op. */
 int gpz_batch_destroy(gpz_batch *b);
 
 /* Optional kernel timing with HIP events recorded on the launch stream.

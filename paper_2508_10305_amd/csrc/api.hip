@@ -214,7 +214,11 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
         if (h_out_bytes) *h_out_bytes = total;
         if (rc == GPZ_OK && total > cap) rc = GPZ_ENOSPC;
     }
-    if (owned) (void)hipFree(ws);
+    if (owned) {
+        // kernels already queued may still use the workspace, also after an error
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ws);
+    }
     return rc;
 }
 
@@ -335,7 +339,10 @@ int gpz_decompress(const void* d_in, uint64_t in_bytes, float* const* h_fields_o
     uint32_t e = 0;
     if (rc == GPZ_OK) rc = to_status(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s));
     if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
-    if (owned) (void)hipFree(err);
+    if (owned) {
+        if (rc != GPZ_OK) (void)hipStreamSynchronize(s);  // queued kernels may use the flag
+        (void)hipFree(err);
+    }
     if (rc == GPZ_OK && e) rc = GPZ_ECORRUPT;
     return rc;
 }
@@ -374,6 +381,7 @@ int gpz_error_stats(const float* const* h_orig, const float* const* h_recon,
     if (rc == GPZ_OK)
         rc = to_status(hipMemcpyAsync(h.data(), acc, 24ull * nfields, hipMemcpyDeviceToHost, s));
     if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    else (void)hipStreamSynchronize(s);  // queued kernels may still use the buffer
     (void)hipFree(acc);
     if (rc) return rc;
     for (uint32_t f = 0; f < nfields; f++) {
@@ -424,6 +432,7 @@ int gpz_stream_stats(const void* d_in, uint64_t in_bytes, uint64_t n, uint32_t n
     if (rc == GPZ_OK)
         rc = to_status(hipMemcpyAsync(h.data(), acc, 8ull * (nfields + 2), hipMemcpyDeviceToHost, s));
     if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    else (void)hipStreamSynchronize(s);  // queued kernels may still use the buffer
     (void)hipFree(acc);
     if (rc) return rc;
     if (h[nfields + 1] & 0xFFFFFFFFull) return GPZ_ECORRUPT;
@@ -450,6 +459,7 @@ int gpz_field_range(const float* const* h_fields, uint64_t n, uint32_t nfields, 
     if (rc == GPZ_OK)
         rc = to_status(hipMemcpyAsync(h.data(), keys, 8ull * nfields, hipMemcpyDeviceToHost, s));
     if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    else (void)hipStreamSynchronize(s);  // queued kernels may still use the buffer
     (void)hipFree(keys);
     if (rc) return rc;
     for (uint32_t f = 0; f < nfields; f++) {

@@ -432,6 +432,7 @@ const uint32_t* gpz_batch_errors(const gpz_batch* b) { return b ? b->d_errors : 
 
 int gpz_batch_destroy(gpz_batch* b) {
     if (!b) return GPZ_OK;
+    (void)hipDeviceSynchronize();  // launches of this batch may still be queued
     if (b->g_comp) (void)hipGraphExecDestroy(b->g_comp);
     if (b->g_dec) (void)hipGraphExecDestroy(b->g_dec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
