@@ -152,7 +152,20 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
     __syncthreads();
     if (active && shl != 0u && w0 < nwords) atomicOr(&stage[w0], first << shl);
     __syncthreads();
-    for (uint32_t i = lane; i < nwords; i += 64) dst[i] = stage[i];
+    // Copy out four words per lane at a time: the four staging reads are all
+    // issued before the stores, so they cost one LDS round trip, not four.
+    // Reads past nwords stay inside the staging buffer (its size is checked
+    // against the largest array, B values of 24 bits) and are never stored.
+    for (uint32_t i0 = 0; i0 < nwords; i0 += 256) {
+        uint32_t t[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) t[u] = stage[i0 + 64 * u + lane];
+        // keeps the compiler from sinking a read into its store's branch
+        asm volatile("" : : "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3]));
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (i0 + 64 * u + lane < nwords) dst[i0 + 64 * u + lane] = t[u];
+    }
     __syncthreads();
 }
 
@@ -202,14 +215,16 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
                                 c[4 * k + 3] + before);
     }
     __syncthreads();
+    // All counter reads are issued before the first scatter store: a store
+    // between them would make every read wait for the one before it.
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        if (FULL || lane * ITEMS + j < nb) {
-            uint32_t d = (kv[j] >> (16 + sh)) & (kDigits - 1);
-            uint32_t dest = cnt[counter_addr(d, lane)] + rank[j];
-            kvbuf[pad_addr<ITEMS>(dest)] = kv[j];
-        }
+        uint32_t d = (kv[j] >> (16 + sh)) & (kDigits - 1);
+        rank[j] += cnt[counter_addr(d, lane)];
     }
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++)
+        if (FULL || lane * ITEMS + j < nb) kvbuf[pad_addr<ITEMS>(rank[j])] = kv[j];
     __syncthreads();
     const uint4* mine = reinterpret_cast<const uint4*>(kvbuf + lane * (ITEMS + 4));
 #pragma unroll
@@ -221,6 +236,56 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
         kv[4 * k + 3] = t.w;
     }
     __syncthreads();
+}
+
+// Runs of the sorted segment IDs (Sec. 4.3): uniq[k] is the k-th distinct ID
+// and start[k] the sorted position where its run begins, k < U.  Lane l
+// takes runs l*ITEMS .. l*ITEMS+ITEMS-1 (0 beyond U).  Each lane reads its
+// ITEMS words with 16-byte loads, unconditionally (the buffers hold B words,
+// entries from U on are ignored), and gets the neighbouring lane's boundary
+// word by a shuffle, so no read waits for another.
+template <int ITEMS>
+__device__ __forceinline__ void load_runs(const uint32_t* src, uint32_t lane,
+                                          uint32_t (&r)[ITEMS]) {
+    const uint4* p = reinterpret_cast<const uint4*>(src + lane * ITEMS);
+#pragma unroll
+    for (int k = 0; k < ITEMS / 4; k++) {
+        uint4 t = p[k];
+        r[4 * k + 0] = t.x;
+        r[4 * k + 1] = t.y;
+        r[4 * k + 2] = t.z;
+        r[4 * k + 3] = t.w;
+    }
+}
+
+// ID gaps minus one; the first ID counts from -1, so its gap is the ID.
+template <int ITEMS>
+__device__ __forceinline__ void run_gaps(const uint32_t* uniq, uint32_t U, uint32_t lane,
+                                         uint32_t (&v)[ITEMS]) {
+    uint32_t r[ITEMS];
+    load_runs<ITEMS>(uniq, lane, r);
+    uint32_t before = (uint32_t)__shfl_up((int)r[ITEMS - 1], 1);
+    if (lane == 0) before = 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint32_t i = lane * ITEMS + j;
+        v[j] = i < U ? r[j] - (j ? r[j - 1] : before) - 1u : 0u;
+    }
+}
+
+// Run lengths minus one; the last run ends at the block's particle count nb.
+template <int ITEMS>
+__device__ __forceinline__ void run_counts(const uint32_t* start, uint32_t U, uint32_t nb,
+                                           uint32_t lane, uint32_t (&v)[ITEMS]) {
+    uint32_t r[ITEMS];
+    load_runs<ITEMS>(start, lane, r);
+    const uint32_t after = (uint32_t)__shfl_down((int)r[0], 1);
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const uint32_t i = lane * ITEMS + j;
+        const uint32_t next = i + 1 == U ? nb : (j + 1 < ITEMS ? r[j + 1] : after);
+        v[j] = i < U ? next - r[j] - 1u : 0u;
+    }
 }
 
 // ------------------------------------------------------------ compaction
@@ -443,21 +508,18 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         }
     }
     __syncthreads();
-    if (lane == 0) start[U] = nb;
-    __syncthreads();
     // delta coding of the distinct IDs (stored as delta - 1) and counts - 1:
     // widths now, values again when they are packed
     uint32_t w_gap, w_cnt;
     {
+        uint32_t g[ITEMS], c[ITEMS];
+        run_gaps<ITEMS>(uniq, U, lane, g);
+        run_counts<ITEMS>(start, U, nb, lane, c);
         uint32_t gmax = 0, cmax = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
-            uint32_t i = lane * ITEMS + j;
-            if (i < U) {
-                uint32_t up = i ? uniq[i - 1] : 0xFFFFFFFFu;
-                gmax = max(gmax, uniq[i] - up - 1u);
-                cmax = max(cmax, start[i + 1] - start[i] - 1u);
-            }
+            gmax = max(gmax, g[j]);
+            cmax = max(cmax, c[j]);
         }
         w_gap = bit_width(wave_max_u32(gmax));
         w_cnt = bit_width(wave_max_u32(cmax));
@@ -477,16 +539,8 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         if (arr < 2) {
             count = U;
             w = arr == 0 ? w_gap : w_cnt;
-#pragma unroll
-            for (int j = 0; j < ITEMS; j++) {
-                uint32_t i = lane * ITEMS + j;
-                uint32_t v = 0;
-                if (i < U) {
-                    if (arr == 0) v = uniq[i] - (i ? uniq[i - 1] : 0xFFFFFFFFu) - 1u;
-                    else v = start[i + 1] - start[i] - 1u;
-                }
-                vals[j] = v;
-            }
+            if (arr == 0) run_gaps<ITEMS>(uniq, U, lane, vals);
+            else run_counts<ITEMS>(start, U, nb, lane, vals);
             if (pos + words_for(count, w) > cap) {
                 over = true;
                 break;
@@ -607,6 +661,8 @@ struct EncodeSmem {
     static constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
     static constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
     static constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
+    // kvbuf doubles as the packer's staging buffer, read in steps of 256 words
+    static_assert((48 * ITEMS + 255) / 256 * 256 <= kKvWords, "staging reads stay in kvbuf");
     __align__(16) uint32_t kvbuf[kKvWords];
     __align__(16) uint32_t work[kWorkWords];
 };
