@@ -111,11 +111,9 @@ __device__ __forceinline__ float quantize_field(const float (&v)[ITEMS], uint32_
 // segment starts inside a word ORs its part in after a barrier.  The staged
 // words are then copied to dst with coalesced stores.
 template <int ITEMS>
-__device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t count, uint32_t w,
-                                           uint32_t* __restrict__ dst, uint32_t* stage,
-                                           uint32_t lane) {
-    const uint32_t nwords = words_for(count, w);
-    if (nwords == 0) return;
+__device__ __forceinline__ void pack_generic(const uint32_t (&v)[ITEMS], uint32_t nwords,
+                                             uint32_t count, uint32_t w, uint32_t* stage,
+                                             uint32_t lane) {
     const bool active = lane * ITEMS < count;
     const uint32_t S = lane * ITEMS * w;            // first bit of the lane's segment
     const uint32_t w0 = S >> 5, shl = S & 31u;
@@ -151,6 +149,71 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
     }
     __syncthreads();
     if (active && shl != 0u && w0 < nwords) atomicOr(&stage[w0], first << shl);
+}
+
+// The same packing for 16 values per lane at a width W known at compile
+// time: every shift is a constant and no branch depends on the bit position.
+// Lane l's values take bits [16*W*l, 16*W*(l+1)) of the array.  For even W
+// that is W/2 whole words.  For odd W the lanes of a pair 2m, 2m+1 share one
+// word (the even lane's last, the odd lane's first): the even lane completes
+// it with the odd lane's low 16 bits, moved over by a DPP lane shift within
+// the row, and stores it.  Every lane packs (values past the array's count
+// are zero), and words past the array's end land in the staging buffer
+// without being copied out.
+template <int W>
+__device__ __forceinline__ void pack16(const uint32_t (&v)[16], uint32_t* stage, uint32_t lane) {
+    constexpr int NS = (16 * W + 31) / 32;  // words of the segment, from its first bit
+    uint32_t s[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) s[k] = 0u;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const int bit = j * W, k = bit >> 5, sh = bit & 31;
+        s[k] |= v[j] << sh;
+        if (sh + W > 32) s[k + 1] |= v[j] >> (32 - sh);
+    }
+    if constexpr (W % 2 == 0) {
+        uint32_t* dst = stage + lane * (W / 2);
+#pragma unroll
+        for (int k = 0; k < W / 2; k++) dst[k] = s[k];
+    } else {
+        constexpr int H = (W - 1) / 2;  // whole words of an even lane before the shared one
+        const bool odd = (lane & 1u) != 0u;
+        const uint32_t nxt = dpp<kRowShl1>(s[0] << 16);
+        uint32_t* dst = stage + ((lane * W) >> 1);
+#pragma unroll
+        for (int t = 0; t <= H; t++) {
+            const uint32_t ev = t < H ? s[t] : (s[H] | nxt);
+            const uint32_t od = t ? __builtin_amdgcn_alignbit(s[t], s[t - 1], 16) : 0u;
+            if (t > 0 || !odd) dst[t] = odd ? od : ev;
+        }
+    }
+}
+
+#define GPZ_PACK16_CASE(W) \
+    case W: pack16<W>(v, stage, lane); break;
+
+// Fixed-length packing of one array into dst (Sec. 4.3), staged in LDS and
+// copied out with coalesced stores.
+template <int ITEMS>
+__device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t count, uint32_t w,
+                                           uint32_t* __restrict__ dst, uint32_t* stage,
+                                           uint32_t lane) {
+    const uint32_t nwords = words_for(count, w);
+    if (nwords == 0) return;
+    if constexpr (ITEMS == 16) {
+        switch (w) {
+            GPZ_PACK16_CASE(1) GPZ_PACK16_CASE(2) GPZ_PACK16_CASE(3) GPZ_PACK16_CASE(4)
+            GPZ_PACK16_CASE(5) GPZ_PACK16_CASE(6) GPZ_PACK16_CASE(7) GPZ_PACK16_CASE(8)
+            GPZ_PACK16_CASE(9) GPZ_PACK16_CASE(10) GPZ_PACK16_CASE(11) GPZ_PACK16_CASE(12)
+            GPZ_PACK16_CASE(13) GPZ_PACK16_CASE(14) GPZ_PACK16_CASE(15) GPZ_PACK16_CASE(16)
+            GPZ_PACK16_CASE(17) GPZ_PACK16_CASE(18) GPZ_PACK16_CASE(19) GPZ_PACK16_CASE(20)
+            GPZ_PACK16_CASE(21) GPZ_PACK16_CASE(22) GPZ_PACK16_CASE(23) GPZ_PACK16_CASE(24)
+            default: pack_generic<ITEMS>(v, nwords, count, w, stage, lane); break;
+        }
+    } else {
+        pack_generic<ITEMS>(v, nwords, count, w, stage, lane);
+    }
     __syncthreads();
     // Copy out four words per lane at a time: the four staging reads are all
     // issued before the stores, so they cost one LDS round trip, not four.

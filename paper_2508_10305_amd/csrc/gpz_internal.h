@@ -111,6 +111,7 @@ constexpr int kQuadSwap2 = 0x4E;      // quad_perm [2,3,0,1]
 constexpr int kRowHalfMirror = 0x141;
 constexpr int kRowMirror = 0x140;
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowShl1 = 0x101;  // lane i receives lane i+1 of its row
 constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
 
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {

@@ -119,6 +119,36 @@ def test_specials_and_outliers(gpz, orc):
         check_case(gpz, orc, host, eb, label=f"specials eb={eb}")
 
 
+@pytest.mark.parametrize("B", [256, 512, 1024, 2048])
+def test_every_packing_width(gpz, orc, B):
+    """Every fixed-length width 1..24 of a field array, in full and partial
+    blocks: with eb = 0.5 the grid step is 1, so integer values k are their
+    own codes, and block b of field 1 holds codes of exactly 1 + b % 24 bits
+    (field 2 the mirror width, field 3 random widths)."""
+    rng = np.random.default_rng(B)
+    nblocks = 49
+    n = nblocks * B - B // 2 - 3
+    host = [rng.random(n).astype(np.float32)]  # the key field
+    for f in range(3):
+        x = np.empty(n, np.float32)
+        for b in range(nblocks):
+            lo, hi = b * B, min(n, (b + 1) * B)
+            w = [1 + b % 24, 24 - b % 24, int(rng.integers(1, 25))][f]
+            k = rng.integers(0, 1 << w, hi - lo)
+            k[rng.integers(0, hi - lo)] = 0
+            k[rng.integers(0, hi - lo)] = (1 << w) - 1
+            x[lo:hi] = k.astype(np.float32)
+        host.append(x)
+    eb = np.array([1e-3, 0.5, 0.5, 0.5], np.float32)
+    seen = set()
+    for b in range(nblocks):
+        tr = orc.block_trace([f[b * B:(b + 1) * B] for f in host], eb, KF=1)
+        assert tr["w"][1] == 1 + b % 24 and tr["w"][2] == 24 - b % 24, f"block {b}: {tr['w']}"
+        seen.update(int(w) for w in tr["w"])
+    assert seen >= set(range(1, 25))
+    check_case(gpz, orc, host, eb, B=B, KF=1, label=f"widths B={B}")
+
+
 def test_raw_fallback_and_constant(gpz, orc):
     rng = np.random.default_rng(6)
     host = [rng.random(4000).astype(np.float32) for _ in range(2)]
