@@ -160,8 +160,11 @@ __device__ __forceinline__ void pack_generic(const uint32_t (&v)[ITEMS], uint32_
 // the row, and stores it.  Every lane packs (values past the array's count
 // are zero), and words past the array's end land in the staging buffer
 // without being copied out.
+// `dst` is the lane's first word in the staging buffer, stage + lane*W/2
+// (rounded down), computed by the caller from the run-time width so that the
+// compiler has no per-width address to keep live across the field loop.
 template <int W>
-__device__ __forceinline__ void pack16(const uint32_t (&v)[16], uint32_t* stage, uint32_t lane) {
+__device__ __forceinline__ void pack16(const uint32_t (&v)[16], uint32_t* dst, uint32_t lane) {
     constexpr int NS = (16 * W + 31) / 32;  // words of the segment, from its first bit
     uint32_t s[NS];
 #pragma unroll
@@ -173,14 +176,12 @@ __device__ __forceinline__ void pack16(const uint32_t (&v)[16], uint32_t* stage,
         if (sh + W > 32) s[k + 1] |= v[j] >> (32 - sh);
     }
     if constexpr (W % 2 == 0) {
-        uint32_t* dst = stage + lane * (W / 2);
 #pragma unroll
         for (int k = 0; k < W / 2; k++) dst[k] = s[k];
     } else {
         constexpr int H = (W - 1) / 2;  // whole words of an even lane before the shared one
         const bool odd = (lane & 1u) != 0u;
         const uint32_t nxt = dpp<kRowShl1>(s[0] << 16);
-        uint32_t* dst = stage + ((lane * W) >> 1);
 #pragma unroll
         for (int t = 0; t <= H; t++) {
             const uint32_t ev = t < H ? s[t] : (s[H] | nxt);
@@ -191,7 +192,7 @@ __device__ __forceinline__ void pack16(const uint32_t (&v)[16], uint32_t* stage,
 }
 
 #define GPZ_PACK16_CASE(W) \
-    case W: pack16<W>(v, stage, lane); break;
+    case W: pack16<W>(v, first, lane); break;
 
 // Fixed-length packing of one array into dst (Sec. 4.3), staged in LDS and
 // copied out with coalesced stores.
@@ -202,6 +203,7 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
     const uint32_t nwords = words_for(count, w);
     if (nwords == 0) return;
     if constexpr (ITEMS == 16) {
+        uint32_t* first = stage + ((lane * w) >> 1);
         switch (w) {
             GPZ_PACK16_CASE(1) GPZ_PACK16_CASE(2) GPZ_PACK16_CASE(3) GPZ_PACK16_CASE(4)
             GPZ_PACK16_CASE(5) GPZ_PACK16_CASE(6) GPZ_PACK16_CASE(7) GPZ_PACK16_CASE(8)
@@ -299,6 +301,21 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
         kv[4 * k + 3] = t.w;
     }
     __syncthreads();
+}
+
+// A field's codes (q | outlier << 31 per value) into lane l's LDS row, with
+// the largest code under `mask` and the number of outliers.
+template <int ITEMS>
+__device__ __forceinline__ void stage_codes(const uint32_t (&q)[ITEMS], uint32_t mask, uint4* mine,
+                                            uint32_t& vmax, uint32_t& no) {
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        vmax = max(vmax, q[j] & mask);
+        no += q[j] >> 31;
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS / 4; k++)
+        mine[k] = make_uint4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
 }
 
 // Runs of the sorted segment IDs (Sec. 4.3): uniq[k] is the k-th distinct ID
@@ -610,34 +627,41 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             }
             __syncthreads();  // uniq/start reads done before `work` is reused
         } else {
-            uint32_t q[ITEMS];
-            float lo;
-            uint32_t mask;
-            if (f < KF) {
-#pragma unroll
-                for (int j = 0; j < ITEMS; j++)
-                    q[j] = f == 0 ? qk[0][j] : (f == 1 ? qk[1][j] : qk[2][j]);
-                lo = f == 0 ? lok[0] : (f == 1 ? lok[1] : lok[2]);
-                const uint32_t s = f == 0 ? sk[0] : (f == 1 ? sk[1] : sk[2]);
-                mask = (1u << s) - 1u;
-            } else if (f - KF < 3) {
-                const uint32_t e = f - KF;
-#pragma unroll
-                for (int j = 0; j < ITEMS; j++)
-                    q[j] = e == 0 ? qo[0][j] : (e == 1 ? qo[1][j] : qo[2][j]);
-                lo = e == 0 ? loo[0] : (e == 1 ? loo[1] : loo[2]);
-                mask = 0xFFFFFFu;
-            } else {
-                float x[ITEMS];
-                load_block<ITEMS, FULL>(a.x[f], base, nb, lane, x);
-                lo = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[f], a.twoeb[f], a.eb[f], q);
-                mask = 0xFFFFFFu;
-            }
-            uint32_t vmax = 0, no = 0;
-#pragma unroll
-            for (int j = 0; j < ITEMS; j++) {
-                vmax = max(vmax, q[j] & mask);
-                no += q[j] >> 31;
+            float lo = 0.0f;
+            uint32_t mask = 0xFFFFFFu, vmax = 0, no = 0;
+            // The field's codes go to LDS in input order (for the permutation
+            // below), with their largest value under the mask and their
+            // outlier count.  Key fields and the early fields are already in
+            // registers: one wave-uniform branch per source, each reading its
+            // own registers (the empty asm keeps the compiler from merging the
+            // branches into a select per value).  Later fields are loaded and
+            // quantized here.
+            uint4* mine = reinterpret_cast<uint4*>(work + lane * (ITEMS + 4));
+            const uint32_t src = f < KF ? f : 3 + (f - KF);
+            switch (src) {
+#define GPZ_STAGE(N, QA, LO, MASK)                              \
+    case N:                                                     \
+        lo = LO;                                                \
+        mask = MASK;                                            \
+        stage_codes<ITEMS>(QA, mask, mine, vmax, no);           \
+        asm volatile("");                                       \
+        break;
+                GPZ_STAGE(0, qk[0], lok[0], (1u << sk[0]) - 1u)
+                GPZ_STAGE(1, qk[1], lok[1], (1u << sk[1]) - 1u)
+                GPZ_STAGE(2, qk[2], lok[2], (1u << sk[2]) - 1u)
+                GPZ_STAGE(3, qo[0], loo[0], 0xFFFFFFu)
+                GPZ_STAGE(4, qo[1], loo[1], 0xFFFFFFu)
+                GPZ_STAGE(5, qo[2], loo[2], 0xFFFFFFu)
+#undef GPZ_STAGE
+                default: {
+                    uint32_t q[ITEMS];
+                    float x[ITEMS];
+                    load_block<ITEMS, FULL>(a.x[f], base, nb, lane, x);
+                    lo = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[f], a.twoeb[f], a.eb[f],
+                                                     q);
+                    stage_codes<ITEMS>(q, mask, mine, vmax, no);
+                    break;
+                }
             }
             w = bit_width(wave_max_u32(vmax));
             nout = wave_sum_u32(no);
@@ -652,10 +676,6 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             }
             pos += 2;
             // permute to sorted order through LDS
-            uint4* mine = reinterpret_cast<uint4*>(work + lane * (ITEMS + 4));
-#pragma unroll
-            for (int k = 0; k < ITEMS / 4; k++)
-                mine[k] = make_uint4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < ITEMS; j++)
