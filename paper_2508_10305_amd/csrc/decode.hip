@@ -24,19 +24,43 @@ __device__ __forceinline__ bool eb_ok(float eb) {
     return __builtin_isfinite(eb) && eb >= 0x1p-120f && eb <= 0x1p120f;
 }
 
-// Copy `count` words from global memory into LDS (coalesced, 4 in flight).
+// Copy `count` words (at most 64*L) from global memory into LDS with
+// coalesced loads, all issued before the first LDS store, so the copy costs
+// one memory round trip.  The number of 64-word steps selects a fully
+// unrolled copy (a wave-uniform choice); inside the last step the lanes past
+// the end load the array's last word again (so every load stays in bounds)
+// and store it past the end, where the buffer still has room.  Offsets are
+// 32-bit byte offsets from the array start, so each load takes the array's
+// scalar base address and one offset register.
+template <int N>
+__device__ __forceinline__ void stage_steps(uint32_t* __restrict__ dst,
+                                            const uint32_t* __restrict__ src, uint32_t count,
+                                            uint32_t ln) {
+    const uint8_t* b = reinterpret_cast<const uint8_t*>(src);
+    uint32_t t[N];
+#pragma unroll
+    for (int u = 0; u < N; u++)
+        t[u] = *reinterpret_cast<const uint32_t*>(b + 4u * min(ln + 64u * u, count - 1));
+#pragma unroll
+    for (int u = 0; u < N; u++) dst[ln + 64u * u] = t[u];
+}
+
+template <int N>
+__device__ __forceinline__ void stage_pick(uint32_t steps, uint32_t* __restrict__ dst,
+                                           const uint32_t* __restrict__ src, uint32_t count,
+                                           uint32_t ln) {
+    if constexpr (N > 0) {
+        if (steps == N) stage_steps<N>(dst, src, count, ln);
+        else stage_pick<N - 1>(steps, dst, src, count, ln);
+    }
+}
+
+template <int L>
 __device__ __forceinline__ void stage_words(uint32_t* __restrict__ dst,
                                             const uint32_t* __restrict__ src, uint32_t count,
                                             uint32_t lane) {
-    uint32_t k = lane;
-    for (; k + 192 < count; k += 256) {
-        uint32_t a = src[k], b = src[k + 64], c = src[k + 128], d = src[k + 192];
-        dst[k] = a;
-        dst[k + 64] = b;
-        dst[k + 128] = c;
-        dst[k + 192] = d;
-    }
-    for (; k < count; k += 64) dst[k] = src[k];
+    if (count == 0) return;
+    stage_pick<L>((count + 63) / 64, dst, src, count, lane);
 }
 
 // Value i of a fixed-length array of width w held in LDS (bits [i*w, i*w+w)).
@@ -64,6 +88,9 @@ struct DecodeSmem {
     // occupancy.
     static constexpr uint32_t kA = kWords > kPadB ? kWords : kPadB;
     static constexpr uint32_t kBuf = kA > B ? kA : B;
+    // 64-word steps of the widest array, which stage_words fills whole
+    static constexpr int kSteps = (int)((kWords + 63) / 64);
+    static_assert(64 * kSteps <= kBuf, "staged steps stay inside buf");
     uint32_t buf[kBuf];
 };
 
@@ -155,7 +182,7 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
     }
 
     // ---- undo delta + run-length coding (Sec. 4.3)
-    stage_words(words, rec + 2, gw + cw, lane);
+    stage_words<DecodeSmem<ITEMS>::kSteps>(words, rec + 2, gw + cw, lane);
     __syncthreads();
     uint32_t g1[ITEMS], c1[ITEMS];
     uint32_t gs = 0, cs = 0;
@@ -253,7 +280,7 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
         }
         const float twoeb = 2.0f * u2f(ebt[f]);
         __syncthreads();  // previous users of `words` are done
-        stage_words(words, rec + pos + 2, pw, lane);
+        stage_words<DecodeSmem<ITEMS>::kSteps>(words, rec + pos + 2, pw, lane);
         __syncthreads();
         const uint32_t mask = low_mask(w);
         const uint32_t kmask = (1u << K) - 1u;

@@ -76,13 +76,31 @@ __device__ __forceinline__ void load_block(const float* __restrict__ x, uint64_t
     }
 }
 
-// Quantize one field of the block: q | outlier << 31 per value (0 beyond the
-// block); returns the block minimum lo (finite values only; zero and "none"
-// give +0).
+// A field of the block after quantization: its minimum lo, the largest code
+// over the block's particles, and whether no value is an outlier.
+struct FieldCodes {
+    float lo;
+    uint32_t qmax;
+    bool clean;
+};
+
+// Quantize one field of the block (Sec. 4.1).  Codes are returned as
+// 2*q + outlier per value (0 beyond the block).
+//
+// Fast path, exact for a field without outliers.  Every finite value lies at
+// or above the block minimum lo, so t = (x - lo) * inv is never below -0, and
+// because no float32 lies strictly between 2^24-1 and 2^24, t <= 2^24-1 holds
+// exactly when rint(t) <= 2^24-1.  So a value is on the grid exactly when the
+// float32 error of fma(rint(t), 2eb, lo) is below eb and rint(t) does not
+// exceed 2^24-1 (a t out of range is NaN, infinite or at least 2^24, and
+// fails one of the two).  With q = rint(t) for every value of the field,
+// fma(q, 2eb, lo) is the reconstruction the quantizer defines (q = -0 and
+// q = +0 give the same result, as lo is never -0).  When any value fails,
+// the whole field is quantized again with the quantizer's own steps.
 template <int ITEMS, bool FULL>
-__device__ __forceinline__ float quantize_field(const float (&v)[ITEMS], uint32_t nb,
-                                                uint32_t lane, float inv, float twoeb, float eb,
-                                                uint32_t (&q)[ITEMS]) {
+__device__ __forceinline__ FieldCodes quantize_field(const float (&v)[ITEMS], uint32_t nb,
+                                                     uint32_t lane, float inv, float twoeb,
+                                                     float eb, uint32_t (&q)[ITEMS]) {
     float m = __builtin_inff();
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
@@ -91,14 +109,31 @@ __device__ __forceinline__ float quantize_field(const float (&v)[ITEMS], uint32_
     }
     m = wave_min_f32(m);
     const float lo = (m == __builtin_inff() || m == 0.0f) ? 0.0f : m;
+    bool good = true;
+    float rmax = 0.0f;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        bool o;
-        uint32_t qq = quantize(v[j], lo, inv, twoeb, eb, o);
-        qq |= (uint32_t)o << 31;
-        q[j] = (FULL || lane * ITEMS + j < nb) ? qq : 0u;
+        const bool valid = FULL || lane * ITEMS + j < nb;
+        const float r = __builtin_rintf((v[j] - lo) * inv);
+        const float xr = __builtin_fmaf(r, twoeb, lo);
+        good = good & (!valid | (__builtin_fabsf(xr - v[j]) < eb));
+        rmax = fmaxf(rmax, valid ? r : 0.0f);
+        q[j] = valid ? (uint32_t)(r + r) : 0u;
     }
-    return lo;
+    uint32_t qmax = wave_max_u32(rmax <= kQMax ? (uint32_t)rmax : 0xFFFFFFFFu);
+    if (__all(good) && qmax <= 0xFFFFFFu) return {lo, qmax, true};
+    // some value is an outlier: the quantizer's steps, value by value
+    uint32_t mx = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const bool valid = FULL || lane * ITEMS + j < nb;
+        bool o;
+        const uint32_t qq = quantize(v[j], lo, inv, twoeb, eb, o);
+        q[j] = valid ? (qq << 1) | (uint32_t)o : 0u;
+        mx = max(mx, valid ? qq : 0u);
+    }
+    qmax = wave_max_u32(mx);
+    return {lo, qmax, false};
 }
 
 // Fixed-length packing (Sec. 4.3): value i of `count` values of width w
@@ -303,15 +338,20 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
     __syncthreads();
 }
 
-// A field's codes (q | outlier << 31 per value) into lane l's LDS row, with
-// the largest code under `mask` and the number of outliers.
-template <int ITEMS>
-__device__ __forceinline__ void stage_codes(const uint32_t (&q)[ITEMS], uint32_t mask, uint4* mine,
-                                            uint32_t& vmax, uint32_t& no) {
+// A field's codes (2*q + outlier per value) into lane l's LDS row.  A key
+// field also needs the largest of its in-segment offsets (code bits below
+// its segment shift, width bits wide); a field with outliers needs their
+// number.
+template <int ITEMS, bool KEY>
+__device__ __forceinline__ void stage_codes(const uint32_t (&q)[ITEMS], uint32_t width, bool clean,
+                                            uint4* mine, uint32_t& vmax, uint32_t& no) {
+    if (KEY) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        vmax = max(vmax, q[j] & mask);
-        no += q[j] >> 31;
+        for (int j = 0; j < ITEMS; j++) vmax = max(vmax, __builtin_amdgcn_ubfe(q[j], 1u, width));
+    }
+    if (!clean) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) no += q[j] & 1u;
     }
 #pragma unroll
     for (int k = 0; k < ITEMS / 4; k++)
@@ -501,36 +541,34 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 #pragma unroll
     for (int e = 0; e < 3; e++)
         if (KF + e < F) load_block<ITEMS, FULL>(a.x[KF + e], base, nb, lane, xo[e]);
+    // codes are 2*q + outlier (Sec. 4.1)
     uint32_t qk[3][ITEMS];
-    float lok[3];
+    FieldCodes ck[3];
     uint32_t sk[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ax++) {
         sk[ax] = 0;
-        lok[ax] = 0.0f;
+        ck[ax] = {0.0f, 0u, true};
         if ((uint32_t)ax < KF) {
-            lok[ax] = quantize_field<ITEMS, FULL>(xk[ax], nb, lane, a.inv[ax], a.twoeb[ax],
-                                                  a.eb[ax], qk[ax]);
-            uint32_t m = 0;
-#pragma unroll
-            for (int j = 0; j < ITEMS; j++) m = max(m, qk[ax][j] & 0xFFFFFFu);
-            uint32_t W = bit_width(wave_max_u32(m));
+            ck[ax] = quantize_field<ITEMS, FULL>(xk[ax], nb, lane, a.inv[ax], a.twoeb[ax],
+                                                 a.eb[ax], qk[ax]);
+            const uint32_t W = bit_width(ck[ax].qmax);
             sk[ax] = W > K ? W - K : 0;
         } else {
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) qk[ax][j] = 0;
         }
     }
-    // the other early fields: grid index and outlier flag (Sec. 4.1)
+    // the other early fields
     uint32_t qo[3][ITEMS];
-    float loo[3];
+    FieldCodes co[3];
 #pragma unroll
     for (int e = 0; e < 3; e++) {
-        loo[e] = 0.0f;
+        co[e] = {0.0f, 0u, true};
         if (KF + e < F) {
             const uint32_t f = KF + e;
-            loo[e] = quantize_field<ITEMS, FULL>(xo[e], nb, lane, a.inv[f], a.twoeb[f], a.eb[f],
-                                                 qo[e]);
+            co[e] = quantize_field<ITEMS, FULL>(xo[e], nb, lane, a.inv[f], a.twoeb[f], a.eb[f],
+                                                qo[e]);
         } else {
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) qo[e][j] = 0;
@@ -545,7 +583,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         uint32_t key = 0;
 #pragma unroll
         for (int ax = 0; ax < 3; ax++)
-            if ((uint32_t)ax < KF) key = (key << K) | ((qk[ax][j] & 0xFFFFFFu) >> sk[ax]);
+            if ((uint32_t)ax < KF) key = (key << K) | (qk[ax][j] >> (sk[ax] + 1));
         uint32_t i = lane * ITEMS + j;
         kv[j] = (key << 16) | i;
         if (FULL || i < nb) keyor |= key;
@@ -627,44 +665,47 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             }
             __syncthreads();  // uniq/start reads done before `work` is reused
         } else {
-            float lo = 0.0f;
-            uint32_t mask = 0xFFFFFFu, vmax = 0, no = 0;
+            FieldCodes c{0.0f, 0u, true};
+            uint32_t width = 24, vmax = 0, no = 0;
+            bool key = false;
             // The field's codes go to LDS in input order (for the permutation
-            // below), with their largest value under the mask and their
-            // outlier count.  Key fields and the early fields are already in
+            // below).  Key fields and the early fields are already in
             // registers: one wave-uniform branch per source, each reading its
             // own registers (the empty asm keeps the compiler from merging the
             // branches into a select per value).  Later fields are loaded and
-            // quantized here.
+            // quantized here.  The packed value is the code's in-segment
+            // offset for a key field (its low sk bits), the whole code
+            // otherwise.
             uint4* mine = reinterpret_cast<uint4*>(work + lane * (ITEMS + 4));
             const uint32_t src = f < KF ? f : 3 + (f - KF);
             switch (src) {
-#define GPZ_STAGE(N, QA, LO, MASK)                              \
-    case N:                                                     \
-        lo = LO;                                                \
-        mask = MASK;                                            \
-        stage_codes<ITEMS>(QA, mask, mine, vmax, no);           \
-        asm volatile("");                                       \
+#define GPZ_STAGE(N, QA, C, KEY, WIDTH)                                  \
+    case N:                                                              \
+        c = C;                                                           \
+        key = KEY;                                                       \
+        width = WIDTH;                                                   \
+        stage_codes<ITEMS, KEY>(QA, width, c.clean, mine, vmax, no);     \
+        asm volatile("");                                                \
         break;
-                GPZ_STAGE(0, qk[0], lok[0], (1u << sk[0]) - 1u)
-                GPZ_STAGE(1, qk[1], lok[1], (1u << sk[1]) - 1u)
-                GPZ_STAGE(2, qk[2], lok[2], (1u << sk[2]) - 1u)
-                GPZ_STAGE(3, qo[0], loo[0], 0xFFFFFFu)
-                GPZ_STAGE(4, qo[1], loo[1], 0xFFFFFFu)
-                GPZ_STAGE(5, qo[2], loo[2], 0xFFFFFFu)
+                GPZ_STAGE(0, qk[0], ck[0], true, sk[0])
+                GPZ_STAGE(1, qk[1], ck[1], true, sk[1])
+                GPZ_STAGE(2, qk[2], ck[2], true, sk[2])
+                GPZ_STAGE(3, qo[0], co[0], false, 24u)
+                GPZ_STAGE(4, qo[1], co[1], false, 24u)
+                GPZ_STAGE(5, qo[2], co[2], false, 24u)
 #undef GPZ_STAGE
                 default: {
                     uint32_t q[ITEMS];
                     float x[ITEMS];
                     load_block<ITEMS, FULL>(a.x[f], base, nb, lane, x);
-                    lo = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[f], a.twoeb[f], a.eb[f],
-                                                     q);
-                    stage_codes<ITEMS>(q, mask, mine, vmax, no);
+                    c = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[f], a.twoeb[f], a.eb[f], q);
+                    stage_codes<ITEMS, false>(q, width, c.clean, mine, vmax, no);
                     break;
                 }
             }
-            w = bit_width(wave_max_u32(vmax));
-            nout = wave_sum_u32(no);
+            const float lo = c.lo;
+            w = bit_width(key ? wave_max_u32(vmax) : c.qmax);
+            nout = c.clean ? 0u : wave_sum_u32(no);
             count = nb;
             if (pos + 2 + words_for(nb, w) + 2 * nout > cap) {
                 over = true;
@@ -680,7 +721,8 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 #pragma unroll
             for (int j = 0; j < ITEMS; j++)
                 vals[j] = (FULL || lane * ITEMS + j < nb)
-                              ? work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)] & mask
+                              ? __builtin_amdgcn_ubfe(work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)], 1u,
+                                                      width)
                               : 0u;
         }
         pack_array<ITEMS>(vals, count, w, rec + pos, kvbuf, lane);
@@ -691,7 +733,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 #pragma unroll
             for (int j = 0; j < ITEMS; j++)
                 if ((FULL || lane * ITEMS + j < nb) &&
-                    (work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)] >> 31))
+                    (work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)] & 1u))
                     flags |= 1u << j;
             const uint32_t c = __builtin_popcount(flags);
             uint32_t k = wave_incl_scan_u32(c) - c;

@@ -149,6 +149,35 @@ def test_every_packing_width(gpz, orc, B):
     check_case(gpz, orc, host, eb, B=B, KF=1, label=f"widths B={B}")
 
 
+def test_quantizer_range_boundary(gpz, orc):
+    """Grid indices at the top of the 24-bit range (Sec. 4.1).  With eb = 0.5
+    the grid step is 1: 2^24-1 is on the grid, 2^24 and 2^24+2 are outliers
+    although their reconstruction error is within the bound; -0.0 in a
+    block whose minimum is +0 or -0 is on the grid."""
+    B = 1024
+    rng = np.random.default_rng(12)
+    cases = [
+        [0.0, 16777215.0],             # largest index: on the grid
+        [0.0, 16777216.0],             # t = 2^24: out of range
+        [0.0, 16777216.0, 16777218.0],
+        [5.0, 16777220.0],             # t = 2^24-1 after the minimum shift: on the grid
+        [4.0, 16777220.0],             # t = 2^24 after the minimum shift: out of range
+        [-0.0, 0.0, 3.0],              # signed zeros
+        [-0.0, 7.0],
+    ]
+    host = [rng.random(B * len(cases)).astype(np.float32)]
+    x = np.empty(B * len(cases), np.float32)
+    for b, vals in enumerate(cases):
+        x[b * B:(b + 1) * B] = np.asarray(vals, np.float32)[rng.integers(0, len(vals), B)]
+        x[b * B:b * B + len(vals)] = vals  # every value present
+    host.append(x)
+    eb = np.array([1e-3, 0.5], np.float32)
+    outl = [int(orc.block_trace([f[b * B:(b + 1) * B] for f in host], eb, KF=1)["outlier"][1].sum())
+            for b in range(len(cases))]
+    assert [o > 0 for o in outl] == [False, True, True, False, True, False, False], outl
+    check_case(gpz, orc, host, eb, B=B, KF=1, label="quantizer range boundary")
+
+
 def test_raw_fallback_and_constant(gpz, orc):
     rng = np.random.default_rng(6)
     host = [rng.random(4000).astype(np.float32) for _ in range(2)]
