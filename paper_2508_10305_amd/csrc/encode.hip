@@ -10,8 +10,10 @@
 // Lane layout: lane l owns the ITEMS = B/64 consecutive particles
 // [l*ITEMS, (l+1)*ITEMS) of its block ("blocked"), so per-lane sequential
 // order followed by lane order is input order; that is what makes the LDS
-// radix sort stable.  One wave per workgroup: __syncthreads() only orders LDS
-// traffic, it never waits for another wave.  Full blocks take a path
+// radix sort stable.  One wave per workgroup: LDS traffic between lanes is
+// ordered by wave_lds_sync(), which waits for nothing (a wave's LDS
+// operations execute in issue order); __syncthreads() remains only where
+// global-memory stores of the block must be ordered.  Full blocks take a path
 // without per-item bounds checks; only the last block of a snapshot can be
 // partial.
 #include "gpz_internal.h"
@@ -182,7 +184,7 @@ __device__ __forceinline__ void pack_generic(const uint32_t (&v)[ITEMS], uint32_
         const uint32_t gi = w0 + k;
         if (active && gi <= lastw && gi < nwords) stage[gi] = prev >> (32u - shl);
     }
-    __syncthreads();
+    wave_lds_sync();
     if (active && shl != 0u && w0 < nwords) atomicOr(&stage[w0], first << shl);
 }
 
@@ -251,7 +253,7 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
     } else {
         pack_generic<ITEMS>(v, nwords, count, w, stage, lane);
     }
-    __syncthreads();
+    wave_lds_sync();
     // Copy out four words per lane at a time: the four staging reads are all
     // issued before the stores, so they cost one LDS round trip, not four.
     // Reads past nwords stay inside the staging buffer (its size is checked
@@ -266,7 +268,7 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
         for (int u = 0; u < 4; u++)
             if (i0 + 64 * u + lane < nwords) dst[i0 + 64 * u + lane] = t[u];
     }
-    __syncthreads();
+    wave_lds_sync();
 }
 
 // One stable LSD pass over 5 key bits starting at bit `sh` of the key
@@ -280,7 +282,7 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
     uint4* c4 = reinterpret_cast<uint4*>(cnt);
 #pragma unroll
     for (int k = 0; k < 9; k++) c4[lane * 9 + k] = make_uint4(0, 0, 0, 0);
-    __syncthreads();
+    wave_lds_sync();
     uint32_t rank[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
@@ -288,7 +290,7 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
         if (FULL || lane * ITEMS + j < nb) rank[j] = atomicAdd(&cnt[counter_addr(d, lane)], 1u);
         else rank[j] = 0u;
     }
-    __syncthreads();
+    wave_lds_sync();
     {
         // lane r scans flat entries [32r, 32r+32) stored at 36r..36r+31
         uint4* row = reinterpret_cast<uint4*>(cnt + 36 * lane);
@@ -314,7 +316,7 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
             row[k] = make_uint4(c[4 * k] + before, c[4 * k + 1] + before, c[4 * k + 2] + before,
                                 c[4 * k + 3] + before);
     }
-    __syncthreads();
+    wave_lds_sync();
     // All counter reads are issued before the first scatter store: a store
     // between them would make every read wait for the one before it.
 #pragma unroll
@@ -325,7 +327,7 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
 #pragma unroll
     for (int j = 0; j < ITEMS; j++)
         if (FULL || lane * ITEMS + j < nb) kvbuf[pad_addr<ITEMS>(rank[j])] = kv[j];
-    __syncthreads();
+    wave_lds_sync();
     const uint4* mine = reinterpret_cast<const uint4*>(kvbuf + lane * (ITEMS + 4));
 #pragma unroll
     for (int k = 0; k < ITEMS / 4; k++) {
@@ -335,7 +337,7 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
         kv[4 * k + 2] = t.z;
         kv[4 * k + 3] = t.w;
     }
-    __syncthreads();
+    wave_lds_sync();
 }
 
 // A field's codes (2*q + outlier per value) into lane l's LDS row.  A key
@@ -625,7 +627,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             }
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     // delta coding of the distinct IDs (stored as delta - 1) and counts - 1:
     // widths now, values again when they are packed
     uint32_t w_gap, w_cnt;
@@ -663,7 +665,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
                 over = true;
                 break;
             }
-            __syncthreads();  // uniq/start reads done before `work` is reused
+            wave_lds_sync();  // uniq/start reads done before `work` is reused
         } else {
             FieldCodes c{0.0f, 0u, true};
             uint32_t width = 24, vmax = 0, no = 0;
@@ -717,7 +719,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             }
             pos += 2;
             // permute to sorted order through LDS
-            __syncthreads();
+            wave_lds_sync();
 #pragma unroll
             for (int j = 0; j < ITEMS; j++)
                 vals[j] = (FULL || lane * ITEMS + j < nb)
@@ -749,7 +751,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             }
             pos += 2 * nout;
         }
-        __syncthreads();  // staging reads done before the next field overwrites it
+        wave_lds_sync();  // staging reads done before the next field overwrites it
     }
 
     const bool raw = over || pos >= cap;

@@ -102,6 +102,17 @@ struct DecodeArgs {
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
+// Orders LDS accesses between the lanes of one wave, for workgroups of a
+// single wave.  A wave's LDS operations execute in the order they are
+// issued, so no wait is needed (a workgroup barrier would wait for every
+// outstanding LDS operation); the wavefront-scope fences and the wave
+// barrier only keep the compiler from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
