@@ -7,9 +7,10 @@
 // Each coded array is first copied into LDS with coalesced loads; values are
 // then extracted from LDS.  Outputs are written "striped": lane l produces
 // positions 256k + 4l + {0..3}, so one 16-byte store per lane covers 1 KB of
-// contiguous output per instruction.  Every read of the record is checked
-// against its length first; a malformed record sets the error flag and the
-// block is skipped.
+// contiguous output per instruction.  One wave per workgroup: LDS traffic
+// between its lanes is ordered by wave_lds_sync().  Every read of the record
+// is checked against its length first; a malformed record sets the error
+// flag and the block is skipped.
 #include "gpz_internal.h"
 
 namespace gpz {
@@ -183,7 +184,7 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
 
     // ---- undo delta + run-length coding (Sec. 4.3)
     stage_words<DecodeSmem<ITEMS>::kSteps>(words, rec + 2, gw + cw, lane);
-    __syncthreads();
+    wave_lds_sync();
     uint32_t g1[ITEMS], c1[ITEMS];
     uint32_t gs = 0, cs = 0;
     {
@@ -206,9 +207,9 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
     }
     // mark run starts with their ID; IDs increase with position, so a prefix
     // maximum over positions gives every position its ID
-    __syncthreads();  // the packed gaps and counts are read; `keys` reuses them
+    wave_lds_sync();  // the packed gaps and counts are read; `keys` reuses them
     for (uint32_t p = lane; p < B; p += 64) keys[pad_addr<ITEMS>(p)] = 0u;
-    __syncthreads();
+    wave_lds_sync();
     {
         uint32_t u = gincl - gs, st = cincl - cs;
 #pragma unroll
@@ -221,7 +222,7 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
             }
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     {
         uint32_t key[ITEMS];
         uint32_t run = 0;
@@ -241,14 +242,14 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
         uint32_t carry = wave_incl_max_u32(run);
         carry = (uint32_t)__shfl_up((int)carry, 1);
         if (lane == 0) carry = 0;
-        __syncthreads();
+        wave_lds_sync();
         uint4* kw = reinterpret_cast<uint4*>(keys + lane * (ITEMS + 4));
 #pragma unroll
         for (int g = 0; g < G; g++)
             kw[g] = make_uint4(max(key[4 * g], carry), max(key[4 * g + 1], carry),
                                max(key[4 * g + 2], carry), max(key[4 * g + 3], carry));
     }
-    __syncthreads();
+    wave_lds_sync();
     // striped positions of this lane: p = 256 g + 4 lane + e
     uint32_t skey[ITEMS];
 #pragma unroll
@@ -279,9 +280,9 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
             break;
         }
         const float twoeb = 2.0f * u2f(ebt[f]);
-        __syncthreads();  // previous users of `words` are done
+        wave_lds_sync();  // previous users of `words` are done
         stage_words<DecodeSmem<ITEMS>::kSteps>(words, rec + pos + 2, pw, lane);
-        __syncthreads();
+        wave_lds_sync();
         const uint32_t mask = low_mask(w);
         const uint32_t kmask = (1u << K) - 1u;
         const bool keyf = f < KF;
@@ -298,12 +299,12 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
         if (nout) {
             // patch outliers through LDS (the staging reuses `words`)
             const uint32_t* ol = rec + pos + 2 + pw;
-            __syncthreads();
+            wave_lds_sync();
 #pragma unroll
             for (int g = 0; g < G; g++)
                 reinterpret_cast<uint4*>(ystage)[64 * g + lane] =
                     make_uint4(y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]);
-            __syncthreads();
+            wave_lds_sync();
             bool obad = false;
             for (uint32_t k = lane; k < nout; k += 64) {
                 uint32_t op = ol[2 * k];
@@ -315,7 +316,7 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
                 bad = true;
                 break;
             }
-            __syncthreads();
+            wave_lds_sync();
 #pragma unroll
             for (int g = 0; g < G; g++) {
                 uint4 t = reinterpret_cast<const uint4*>(ystage)[64 * g + lane];
