@@ -226,14 +226,20 @@ void gpz_default_batch_config(gpz_batch_config *c);
 uint64_t gpz_batch_workspace_bytes(const gpz_job *jobs, uint32_t njobs, const gpz_params *p);
 
 /* Creates a batch bound to `jobs` and the caller's workspace d_ws (device,
- * >= gpz_batch_workspace_bytes).  Allocates the batch's device tables and a
- * private non-blocking stream used for graph capture.  *out = NULL on error. */
+ * >= gpz_batch_workspace_bytes).  Allocates the batch's device tables, a
+ * pinned host image of them and a private non-blocking stream used for graph
+ * capture; the tables are on the device when it returns.  *out = NULL on
+ * error. */
 int gpz_batch_create(gpz_batch **out, const gpz_job *jobs, uint32_t njobs, const gpz_params *p,
                      const gpz_batch_config *cfg, void *d_ws, uint64_t ws_bytes);
 
 /* Binds the batch to a new job list within its capacities, without device
  * allocation and without invalidating captured graphs.  Synchronizes
- * `stream` first (earlier work of this batch must have finished). */
+ * `stream` first (earlier work of this batch must have finished), then
+ * queues the new tables on `stream` with one copy from pinned memory and
+ * returns without waiting for it: the batch's next gpz_batch_compress /
+ * gpz_batch_decompress must be issued on the same stream (or on one that
+ * waits for it). */
 int gpz_batch_rebind(gpz_batch *b, const gpz_job *jobs, uint32_t njobs, void *d_ws,
                      uint64_t ws_bytes, void *stream);
 

@@ -8,7 +8,6 @@
 #include <math.h>
 #include <string.h>
 
-#include <vector>
 
 #include "gpz.h"
 #include "gpz_internal.h"
@@ -40,6 +39,12 @@ struct gpz_batch {
     uint64_t* d_total = nullptr;
     uint64_t* d_sizes = nullptr;   // stream size per job
     uint32_t* d_errors = nullptr;  // decode error flag per job
+    // Pinned host image of the job tables and launch descriptor (the first
+    // upload_bytes of `tables`), uploaded with one asynchronous copy per bind;
+    // `uploaded` marks the last copy, after which the image may be rewritten.
+    char* h_tables = nullptr;
+    uint64_t upload_bytes = 0;
+    hipEvent_t uploaded = nullptr;
     hipStream_t capture = nullptr;
     hipGraphExec_t g_comp = nullptr, g_dec = nullptr;
 };
@@ -140,8 +145,16 @@ int capture(gpz_batch* b, int (*enqueue)(gpz_batch*, hipStream_t), hipGraphExec_
     return rc;
 }
 
-// Host image of the tables of a job list, then one upload.
-int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t ws_bytes) {
+template <typename T>
+T* host_image(gpz_batch* b, T* device_ptr) {
+    return reinterpret_cast<T*>(b->h_tables +
+                                (reinterpret_cast<char*>(device_ptr) - static_cast<char*>(b->tables)));
+}
+
+// Host image of the tables of a job list, then one asynchronous upload on
+// stream s (ordered before whatever s runs next).
+int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t ws_bytes,
+         hipStream_t s) {
     const gpz_params& p = b->p;
     const uint32_t B = p.block_size;
     int rc = validate_jobs(jobs, njobs, p);
@@ -157,11 +170,17 @@ int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t
     const uint64_t ws_need = jobs_workspace(jobs, njobs, B);
     if (ws_need > ws_bytes || (ws_need && !d_ws)) return GPZ_EINVAL;
 
-    std::vector<EncodeArgs> enc(njobs);
-    std::vector<ScanArgs> scan(njobs);
-    std::vector<CopyArgs> copy(njobs);
-    std::vector<DecodeArgs> dec(njobs);
-    std::vector<uint32_t> full_prefix(njobs + 1, 0), block_prefix(njobs + 1, 0), tails;
+    // the previous upload must have read the image before it is rewritten
+    if (hipEventSynchronize(b->uploaded) != hipSuccess) return GPZ_EDEVICE;
+    EncodeArgs* enc = host_image(b, b->d_enc);
+    ScanArgs* scan = host_image(b, b->d_scan);
+    CopyArgs* copy = host_image(b, b->d_copy);
+    DecodeArgs* dec = host_image(b, b->d_dec);
+    uint32_t* full_prefix = host_image(b, b->d_full_prefix);
+    uint32_t* block_prefix = host_image(b, b->d_block_prefix);
+    uint32_t* tails = host_image(b, b->d_tail);
+    uint32_t ntail = 0;
+    full_prefix[0] = block_prefix[0] = 0;
     bool can_c = true, can_d = true;
     char* ws = static_cast<char*>(d_ws);
     uint64_t ws_at = 0, blk_at = 0, sup_at = 0;
@@ -172,7 +191,7 @@ int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t
         const uint32_t sw = slot_words_of(F, B);
         full_prefix[j + 1] = full_prefix[j] + (uint32_t)(J.n / B);
         block_prefix[j + 1] = block_prefix[j] + (uint32_t)nb;
-        if (J.n % B) tails.push_back(j);
+        if (J.n % B) tails[ntail++] = j;
         if (J.n > 0 && !J.fields) can_c = false;
         if (J.n > 0 && !J.dec_fields) can_d = false;
         uint32_t* temp = !J.fields ? nullptr
@@ -243,33 +262,22 @@ int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t
         blk_at += nb;
         sup_at += nsuper_of(nb);
     }
-    BatchLaunch L{};
+    BatchLaunch& L = *host_image(b, b->d_launch);
+    L = BatchLaunch{};
     L.njobs = njobs;
     L.total_full = full_prefix[njobs];
     L.total_blocks = block_prefix[njobs];
-    L.ntail = (uint32_t)tails.size();
+    L.ntail = ntail;
     L.tile = b->cfg.tile;
     L.full_prefix = b->d_full_prefix;
     L.block_prefix = b->d_block_prefix;
     L.tail_jobs = b->d_tail;
     L.counter = b->d_counters;
 
-    // uploads on the batch's own non-blocking stream (never the null stream,
-    // which would serialize with the caller's streams)
-    hipError_t e = hipSuccess;
-    auto put = [&](void* dst, const void* src, uint64_t bytes) {
-        if (e == hipSuccess && bytes)
-            e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->capture);
-    };
-    put(b->d_enc, enc.data(), sizeof(EncodeArgs) * njobs);
-    put(b->d_scan, scan.data(), sizeof(ScanArgs) * njobs);
-    put(b->d_copy, copy.data(), sizeof(CopyArgs) * njobs);
-    put(b->d_dec, dec.data(), sizeof(DecodeArgs) * njobs);
-    put(b->d_full_prefix, full_prefix.data(), 4ull * (njobs + 1));
-    put(b->d_block_prefix, block_prefix.data(), 4ull * (njobs + 1));
-    put(b->d_tail, tails.data(), 4ull * tails.size());
-    put(b->d_launch, &L, sizeof(L));
-    if (e == hipSuccess) e = hipStreamSynchronize(b->capture);
+    // one copy from pinned memory, queued on s: it runs after the work
+    // already on s and before the launches that follow
+    hipError_t e = hipMemcpyAsync(b->tables, b->h_tables, b->upload_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(b->uploaded, s);
     if (e != hipSuccess) return GPZ_EDEVICE;
     b->njobs = njobs;
     b->can_compress = can_c;
@@ -381,11 +389,18 @@ int gpz_batch_create(gpz_batch** out, const gpz_job* jobs, uint32_t njobs, const
     b->d_total = reinterpret_cast<uint64_t*>(base + o_tot);
     b->d_sizes = reinterpret_cast<uint64_t*>(base + o_sizes);
     b->d_errors = reinterpret_cast<uint32_t*>(base + o_err);
-    if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+    b->upload_bytes = o_cnt;  // the tables and launch descriptor come first
+    if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->h_tables), b->upload_bytes) != hipSuccess) {
         gpz_batch_destroy(b);
         return GPZ_EDEVICE;
     }
-    rc = bind(b, jobs, njobs, d_ws, ws_bytes);
+    memset(b->h_tables, 0, b->upload_bytes);
+    // the first bind's upload is on the batch's own stream, waited for here
+    // (the caller's streams are not ordered with it)
+    rc = bind(b, jobs, njobs, d_ws, ws_bytes, b->capture);
+    if (rc == GPZ_OK && hipStreamSynchronize(b->capture) != hipSuccess) rc = GPZ_EDEVICE;
     if (rc) {
         gpz_batch_destroy(b);
         return rc;
@@ -399,7 +414,7 @@ int gpz_batch_rebind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_
     if (!b) return GPZ_EINVAL;
     // earlier work of this batch must be done before its tables change
     if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return GPZ_EDEVICE;
-    return bind(b, jobs, njobs, d_ws, ws_bytes);
+    return bind(b, jobs, njobs, d_ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 int gpz_batch_compress(gpz_batch* b, void* stream) {
@@ -436,6 +451,8 @@ int gpz_batch_destroy(gpz_batch* b) {
     if (b->g_comp) (void)hipGraphExecDestroy(b->g_comp);
     if (b->g_dec) (void)hipGraphExecDestroy(b->g_dec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+    if (b->h_tables) (void)hipHostFree(b->h_tables);
     if (b->tables) (void)hipFree(b->tables);
     delete b;
     return GPZ_OK;

@@ -196,14 +196,20 @@ class Server:
         ws = self.arena.view(0, ALIGN)  # every job brings its own workspace
         slot.ws_off, slot.ws_bytes = -1, 0
         with torch.cuda.stream(slot.stream):
+            # Both rebinds come before either launch: a rebind first waits for
+            # the slot's stream (the batch's tables may still be in use), and
+            # after a launch that wait would hold the whole loop until the
+            # launched batch finished.
             if comp:
                 slot.batch_c.rebind([r.fields for r in comp], [r.eb for r in comp],
                                     [r.out for r in comp], workspace=ws, stream=slot.stream,
                                     job_ws=[r.ws for r in comp])
-                slot.batch_c.compress(stream=slot.stream)
             if dec:
                 slot.batch_d.rebind(None, [r.eb for r in dec], [r.stream for r in dec],
                                     dec=[r.out for r in dec], workspace=ws, stream=slot.stream)
+            if comp:
+                slot.batch_c.compress(stream=slot.stream)
+            if dec:
                 slot.batch_d.decompress(stream=slot.stream)
             slot.event = torch.cuda.Event()
             slot.event.record(slot.stream)
@@ -320,7 +326,10 @@ class Server:
                 else:
                     small = lambda r: (r.n + self.B - 1) // self.B <= self.batch_below_blocks
                     take, blocks = [], 0
-                    if small(admitted[0]):
+                    # batch only while more requests wait than streams are
+                    # free: otherwise every request gets a stream of its own
+                    free = sum(1 for sl in self.slots if not sl.busy)
+                    if small(admitted[0]) and len(admitted) > free:
                         # the small admitted requests, in arrival order
                         for r in admitted:
                             if not small(r):
@@ -330,8 +339,9 @@ class Server:
                                 break
                             take.append(r)
                             blocks += nb
-                    # a large request, or a lone small one, gets a plain launch
-                    # (rebinding a batch costs more than a batch of one saves)
+                    # a large request, or a small one that has a stream to
+                    # itself, gets a plain launch (rebinding a batch costs
+                    # more than a batch of one saves)
                     if len(take) <= 1:
                         r = admitted[0]
                         if self._launch_single(slot, r):
