@@ -274,6 +274,12 @@ int gpz_batch_destroy(gpz_batch *b);
 int gpz_set_timing(int enable);
 int gpz_timing_collect(double *total_ms, uint32_t *counts, int nkinds);
 
+/* Like gpz_set_timing, for a subset of the kernel kinds: bit k of mask times
+ * kind k (0 turns timing off; 0x1F is every kind).  Each timed kernel costs
+ * an event pair on its stream, so timing only the kernels of interest keeps
+ * the others' launches unchanged.  GPZ_EINVAL for bits beyond kind 4. */
+int gpz_set_timing_kinds(uint32_t mask);
+
 const char *gpz_strerror(int status);
 
 #ifdef __cplusplus

@@ -25,7 +25,8 @@ EXPORTS = (
     "gpz_decompress_workspace_bytes", "gpz_compress", "gpz_compress_async", "gpz_decompress",
     "gpz_decompress_async", "gpz_bound_check", "gpz_error_stats", "gpz_stream_stats",
     "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
-    "gpz_set_timing", "gpz_timing_collect", "gpz_strerror", "gpz_default_batch_config",
+    "gpz_set_timing", "gpz_set_timing_kinds", "gpz_timing_collect", "gpz_strerror",
+    "gpz_default_batch_config",
     "gpz_batch_workspace_bytes", "gpz_batch_create", "gpz_batch_rebind", "gpz_batch_compress",
     "gpz_batch_decompress", "gpz_batch_sizes", "gpz_batch_errors", "gpz_batch_destroy",
 )
@@ -109,6 +110,8 @@ def _lib():
         L.gpz_inspect.restype = ctypes.c_int
         L.gpz_set_timing.argtypes = [ctypes.c_int]
         L.gpz_set_timing.restype = ctypes.c_int
+        L.gpz_set_timing_kinds.argtypes = [ctypes.c_uint32]
+        L.gpz_set_timing_kinds.restype = ctypes.c_int
         L.gpz_timing_collect.argtypes = [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_uint32), ctypes.c_int]
         L.gpz_timing_collect.restype = ctypes.c_int
@@ -374,11 +377,22 @@ def inspect(prefix: bytes) -> dict:
                 seg_bits=info.seg_bits, key_fields=info.key_fields, nblocks=info.nblocks)
 
 
-def set_timing(enable: bool):
-    _lib().gpz_set_timing(1 if enable else 0)
-
-
 KERNEL_KINDS = ("encode", "prepare", "decode", "scan", "copy")
+
+
+def set_timing(enable: bool, kinds: Optional[Sequence[str]] = None):
+    """Turn kernel timing on or off for this host thread; `kinds` limits it
+    to some of KERNEL_KINDS (each timed kernel costs an event pair)."""
+    if not enable:
+        _check(_lib().gpz_set_timing_kinds(0), "gpz_set_timing_kinds")
+        return
+    if kinds is None:
+        _lib().gpz_set_timing(1)
+        return
+    mask = 0
+    for k in kinds:
+        mask |= 1 << KERNEL_KINDS.index(k)
+    _check(_lib().gpz_set_timing_kinds(mask), "gpz_set_timing_kinds")
 
 
 def timing_collect() -> dict:

@@ -19,16 +19,16 @@ struct TimedLaunch {
     int kind;
     hipEvent_t a, b;
 };
-thread_local bool g_timing = false;
+thread_local uint32_t g_timing = 0;  // bit k: time kernels of kind k
 thread_local std::vector<TimedLaunch> g_log;
 
 struct Timer {
     hipStream_t s;
     bool on;
     TimedLaunch cur{};
-    explicit Timer(hipStream_t st) : s(st), on(g_timing) {}
+    explicit Timer(hipStream_t st) : s(st), on(g_timing != 0) {}
     void begin(int kind) {
-        if (!on) return;
+        if (!on || !((g_timing >> kind) & 1u)) return;
         cur.kind = kind;
         if (hipEventCreate(&cur.a) != hipSuccess) return;
         if (hipEventCreate(&cur.b) != hipSuccess) {
@@ -506,7 +506,13 @@ int gpz_inspect(const void* h_prefix, uint64_t bytes, gpz_info* out) {
 }
 
 int gpz_set_timing(int enable) {
-    g_timing = enable != 0;
+    g_timing = enable != 0 ? (1u << kKinds) - 1u : 0u;
+    return GPZ_OK;
+}
+
+int gpz_set_timing_kinds(uint32_t mask) {
+    if (mask >> kKinds) return GPZ_EINVAL;
+    g_timing = mask;
     return GPZ_OK;
 }
 

@@ -94,6 +94,16 @@ def test_strerror(gpz):
         assert gpz.lib().gpz_strerror(c)
 
 
+def test_timing_kinds_mask(gpz):
+    L = gpz.lib()
+    assert L.gpz_set_timing_kinds(1 << 5) == gpz.GPZ_EINVAL  # no kind 5
+    assert L.gpz_set_timing_kinds(0x1F) == gpz.GPZ_OK
+    assert L.gpz_set_timing_kinds(0) == gpz.GPZ_OK
+    with pytest.raises(ValueError):
+        gpz.set_timing(True, kinds=("no such kernel",))
+    gpz.set_timing(False)
+
+
 def test_batch_and_stats_entry_points_reject_bad_arguments(gpz):
     """Host-side argument checks of the batch, statistics and timing entry
     points: every one returns a status before touching the device."""

@@ -161,6 +161,51 @@ def test_rebind_keeps_graphs_valid(gpz, grid):
     b.close()
 
 
+def test_rebinds_back_to_back_on_one_stream(gpz):
+    """Rebinds queue their table upload on the caller's stream and return
+    without waiting for it: three job lists bound, compressed and decompressed
+    in a row on one side stream, with no host synchronization of our own,
+    must each give the plain results."""
+    from paper_2508_10305_amd.batch import Batch, default_config
+    lists = [make_jobs(31 + k, sizes) for k, sizes in
+             enumerate([[40_000, 3_000], [1_025, 90_000, 7], [64 * 1024, 12_345, 2_048]])]
+    refs = [plain_results(gpz, jobs) for jobs in lists]
+    cfg = default_config()
+    b = Batch.empty(8, 256, config=cfg)
+    s = torch.cuda.Stream()
+    bound = []
+    for k, jobs in enumerate(lists):
+        fields, outs, decs, ebs = [], [], [], []
+        for host, eb in jobs:
+            n, F = host[0].size, len(host)
+            fields.append([torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in host])
+            outs.append(torch.zeros(gpz.max_compressed_bytes(n, F), dtype=torch.uint8,
+                                    device="cuda"))
+            decs.append([torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(F)])
+            ebs.append(eb)
+        ws = torch.empty(Batch.workspace_bytes(fields, ebs, outs, decs), dtype=torch.uint8,
+                         device="cuda")
+        torch.cuda.synchronize()  # inputs are in place before the side stream starts
+        say(f"[case] back-to-back rebind {k}")
+        with torch.cuda.stream(s):
+            b.rebind(fields, ebs, outs, dec=decs, workspace=ws, stream=s)
+            b.compress(stream=s)
+            b.decompress(stream=s)
+            # this list's results leave the batch's size table before the next rebind
+            sizes = b.sizes_device().clone()
+        bound.append((outs, decs, sizes, fields, ws))
+    torch.cuda.synchronize()
+    for k, ((outs, decs, sizes, _, _), ref) in enumerate(zip(bound, refs)):
+        sz = sizes.cpu().numpy()
+        for j, (rs, rout) in enumerate(ref):
+            assert int(sz[j]) == rs.size, f"list {k} job {j} size"
+            assert (outs[j][: rs.size].cpu().numpy() == rs).all(), f"list {k} job {j} stream"
+            for f, ro in enumerate(rout):
+                d = decs[j][f].cpu().numpy()
+                assert (d.view(np.uint32) == ro.view(np.uint32)).all(), f"list {k} job {j} f {f}"
+    b.close()
+
+
 def test_batch_reports_corrupt_stream(gpz):
     jobs = make_jobs(23, [20_000, 20_000])
     b, fields, outs, decs, ebs = build_batch(gpz, jobs)

@@ -435,6 +435,14 @@ def test_kernel_timing_log(gpz, single_pass):
     assert counts == want, counts
     assert all(kt[k][0] > 0 for k in want if want[k])
     assert gpz.timing_collect()["encode"][1] == 0  # the log was cleared
+    # timing a subset of the kinds: only those launches are logged
+    gpz.set_timing(True, kinds=("encode", "decode"))
+    s, _ = gpz.compress(dev, 1e-4, single_pass=single_pass)
+    gpz.decompress(s, 300_000, 3)
+    kt = gpz.timing_collect()
+    gpz.set_timing(False)
+    assert {k: v[1] for k, v in kt.items()} == {"encode": 1, "prepare": 0, "decode": 1,
+                                                "scan": 0, "copy": 0}
 
 
 def test_random_parameters_match_oracle(gpz, orc):
