@@ -361,11 +361,13 @@ __device__ __forceinline__ void stage_codes(const uint32_t (&q)[ITEMS], uint32_t
 }
 
 // Runs of the sorted segment IDs (Sec. 4.3): uniq[k] is the k-th distinct ID
-// and start[k] the sorted position where its run begins, k < U.  Lane l
-// takes runs l*ITEMS .. l*ITEMS+ITEMS-1 (0 beyond U).  Each lane reads its
-// ITEMS words with 16-byte loads, unconditionally (the buffers hold B words,
-// entries from U on are ignored), and gets the neighbouring lane's boundary
-// word by a shuffle, so no read waits for another.
+// and start[k] the sorted position where its run begins, k < U, with
+// start[U] = nb.  Lane l takes runs l*ITEMS .. l*ITEMS+ITEMS-1 (0 beyond U).
+// Each lane reads its ITEMS words with 16-byte loads, unconditionally (the
+// buffers hold B words, entries from U on are ignored), so no read waits for
+// another.  Runs past U are cleared with a per-lane bit mask: a compare per
+// run would give the compiler U-dependent lane masks to keep (and spill)
+// across the whole field loop, so U is also made opaque here.
 template <int ITEMS>
 __device__ __forceinline__ void load_runs(const uint32_t* src, uint32_t lane,
                                           uint32_t (&r)[ITEMS]) {
@@ -380,34 +382,40 @@ __device__ __forceinline__ void load_runs(const uint32_t* src, uint32_t lane,
     }
 }
 
+// Bit j set when run lane*ITEMS + j exists (j < ITEMS <= 32).
+template <int ITEMS>
+__device__ __forceinline__ uint32_t run_mask(uint32_t U, uint32_t lane) {
+    asm volatile("" : "+s"(U));
+    const int c = min(max((int)U - (int)(lane * ITEMS), 0), ITEMS);
+    return c >= 32 ? ~0u : (1u << c) - 1u;
+}
+
 // ID gaps minus one; the first ID counts from -1, so its gap is the ID.
 template <int ITEMS>
 __device__ __forceinline__ void run_gaps(const uint32_t* uniq, uint32_t U, uint32_t lane,
                                          uint32_t (&v)[ITEMS]) {
     uint32_t r[ITEMS];
     load_runs<ITEMS>(uniq, lane, r);
+    const uint32_t m = run_mask<ITEMS>(U, lane);
     uint32_t before = (uint32_t)__shfl_up((int)r[ITEMS - 1], 1);
     if (lane == 0) before = 0xFFFFFFFFu;
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        const uint32_t i = lane * ITEMS + j;
-        v[j] = i < U ? r[j] - (j ? r[j - 1] : before) - 1u : 0u;
-    }
+    for (int j = 0; j < ITEMS; j++)
+        v[j] = (r[j] - (j ? r[j - 1] : before) - 1u) & (uint32_t)__builtin_amdgcn_sbfe(m, j, 1);
 }
 
-// Run lengths minus one; the last run ends at the block's particle count nb.
+// Run lengths minus one: start[i+1] - start[i] - 1 (start[U] = nb).
 template <int ITEMS>
-__device__ __forceinline__ void run_counts(const uint32_t* start, uint32_t U, uint32_t nb,
-                                           uint32_t lane, uint32_t (&v)[ITEMS]) {
+__device__ __forceinline__ void run_counts(const uint32_t* start, uint32_t U, uint32_t lane,
+                                           uint32_t (&v)[ITEMS]) {
     uint32_t r[ITEMS];
     load_runs<ITEMS>(start, lane, r);
-    const uint32_t after = (uint32_t)__shfl_down((int)r[0], 1);
+    const uint32_t after = start[lane * ITEMS + ITEMS];
+    const uint32_t m = run_mask<ITEMS>(U, lane);
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        const uint32_t i = lane * ITEMS + j;
-        const uint32_t next = i + 1 == U ? nb : (j + 1 < ITEMS ? r[j + 1] : after);
-        v[j] = i < U ? next - r[j] - 1u : 0u;
-    }
+    for (int j = 0; j < ITEMS; j++)
+        v[j] = ((j + 1 < ITEMS ? r[j + 1] : after) - r[j] - 1u) &
+               (uint32_t)__builtin_amdgcn_sbfe(m, j, 1);
 }
 
 // ------------------------------------------------------------ compaction
@@ -617,15 +625,16 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         }
         uint32_t incl = wave_incl_scan_u32(nflag);
         U = readlane(incl, 63);
+        // Every item stores, without branches: a run start at its rank k,
+        // any other item to a scratch word of its lane past the tables.
         uint32_t k = incl - nflag;
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
-            if (flag[j]) {
-                uniq[k] = kv[j] >> 16;
-                start[k] = lane * ITEMS + j;
-                k++;
-            }
+            uniq[flag[j] ? k : 2 * B + 64 + lane] = kv[j] >> 16;
+            start[flag[j] ? k : B + 128 + lane] = lane * ITEMS + j;
+            k += flag[j] ? 1u : 0u;
         }
+        if (lane == 0) start[U] = nb;
     }
     wave_lds_sync();
     // delta coding of the distinct IDs (stored as delta - 1) and counts - 1:
@@ -634,7 +643,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     {
         uint32_t g[ITEMS], c[ITEMS];
         run_gaps<ITEMS>(uniq, U, lane, g);
-        run_counts<ITEMS>(start, U, nb, lane, c);
+        run_counts<ITEMS>(start, U, lane, c);
         uint32_t gmax = 0, cmax = 0;
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
@@ -660,7 +669,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             count = U;
             w = arr == 0 ? w_gap : w_cnt;
             if (arr == 0) run_gaps<ITEMS>(uniq, U, lane, vals);
-            else run_counts<ITEMS>(start, U, nb, lane, vals);
+            else run_counts<ITEMS>(start, U, lane, vals);
             if (pos + words_for(count, w) > cap) {
                 over = true;
                 break;
@@ -786,7 +795,9 @@ template <int ITEMS>
 struct EncodeSmem {
     static constexpr uint32_t B = 64 * ITEMS;
     static constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
-    static constexpr uint32_t kWorkA = kCounterWords > 2 * B + 2 ? kCounterWords : 2 * B + 2;
+    // run tables: uniq[0, B), start[0, B] at B, and per-lane scratch words
+    // for the branch-free run stores at 2B + 64 and 2B + 128
+    static constexpr uint32_t kWorkA = kCounterWords > 2 * B + 192 ? kCounterWords : 2 * B + 192;
     static constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
     // kvbuf doubles as the packer's staging buffer, read in steps of 256 words
     static_assert((48 * ITEMS + 255) / 256 * 256 <= kKvWords, "staging reads stay in kvbuf");
