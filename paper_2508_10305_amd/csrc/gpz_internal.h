@@ -143,18 +143,28 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
     }
 
 __device__ __forceinline__ uint32_t op_max(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ __forceinline__ uint32_t op_min(uint32_t a, uint32_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint32_t op_or(uint32_t a, uint32_t b) { return a | b; }
 __device__ __forceinline__ uint32_t op_add(uint32_t a, uint32_t b) { return a + b; }
-__device__ __forceinline__ float op_fmin(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ uint32_t id_u32(uint32_t v) { return v; }
-__device__ __forceinline__ uint32_t f_bits(float v) { return __float_as_uint(v); }
-__device__ __forceinline__ float bits_f(uint32_t v) { return __uint_as_float(v); }
 
 GPZ_WAVE_REDUCE(wave_max_u32, uint32_t, op_max, id_u32, id_u32)
+GPZ_WAVE_REDUCE(wave_min_u32, uint32_t, op_min, id_u32, id_u32)
 GPZ_WAVE_REDUCE(wave_or_u32, uint32_t, op_or, id_u32, id_u32)
 GPZ_WAVE_REDUCE(wave_sum_u32, uint32_t, op_add, id_u32, id_u32)
-GPZ_WAVE_REDUCE(wave_min_f32, float, op_fmin, f_bits, bits_f)
 #undef GPZ_WAVE_REDUCE
+
+// Minimum of non-NaN floats across the wave.  The float is mapped to an
+// unsigned key with the same order (sign bit flipped for positive values,
+// all bits flipped for negative ones), so the reduction runs on integer
+// minimums, which fuse with their DPP lane moves; a float minimum would also
+// quiet its operands at every step.  -0 orders below +0.
+__device__ __forceinline__ float wave_min_f32(float v) {
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t k = u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
+    const uint32_t m = wave_min_u32(k);
+    return __uint_as_float(m ^ (((m >> 31) - 1u) | 0x80000000u));
+}
 
 // Inclusive prefix sum across the wave (lane order).
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
