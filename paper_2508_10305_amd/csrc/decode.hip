@@ -284,18 +284,29 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
         stage_words<DecodeSmem<ITEMS>::kSteps>(words, rec + pos + 2, pw, lane);
         wave_lds_sync();
         const uint32_t mask = low_mask(w);
-        const uint32_t kmask = (1u << K) - 1u;
-        const bool keyf = f < KF;
         uint32_t y[ITEMS];
+        if (f < KF) {
+            // a key field's code: the position's segment (its K bits of the
+            // ID) above the s stored offset bits
 #pragma unroll
-        for (int g = 0; g < G; g++)
+            for (int g = 0; g < G; g++)
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const uint32_t p = 256 * g + 4 * lane + e;
-                uint32_t v = extract(words, p, w, mask);
-                uint32_t q = keyf ? ((((skey[4 * g + e] >> shift) & kmask) << s) | v) : v;
-                y[4 * g + e] = f2u(__builtin_fmaf((float)q, twoeb, lo));
-            }
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t p = 256 * g + 4 * lane + e;
+                    const uint32_t v = extract(words, p, w, mask);
+                    const uint32_t q = (__builtin_amdgcn_ubfe(skey[4 * g + e], shift, K) << s) | v;
+                    y[4 * g + e] = f2u(__builtin_fmaf((float)q, twoeb, lo));
+                }
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; g++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t p = 256 * g + 4 * lane + e;
+                    const uint32_t v = extract(words, p, w, mask);
+                    y[4 * g + e] = f2u(__builtin_fmaf((float)v, twoeb, lo));
+                }
+        }
         if (nout) {
             // patch outliers through LDS (the staging reuses `words`)
             const uint32_t* ol = rec + pos + 2 + pw;
