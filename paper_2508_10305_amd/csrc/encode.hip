@@ -256,17 +256,30 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
     wave_lds_sync();
     // Copy out four words per lane at a time: the four staging reads are all
     // issued before the stores, so they cost one LDS round trip, not four.
+    // Whole 256-word steps store unconditionally, at 32-bit byte offsets from
+    // the array's scalar base; only the last, partial step is predicated.
     // Reads past nwords stay inside the staging buffer (its size is checked
     // against the largest array, B values of 24 bits) and are never stored.
-    for (uint32_t i0 = 0; i0 < nwords; i0 += 256) {
+    uint8_t* const base = reinterpret_cast<uint8_t*>(dst);
+    const uint32_t whole = nwords & ~255u;
+    for (uint32_t i0 = 0; i0 < whole; i0 += 256) {
         uint32_t t[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) t[u] = stage[i0 + 64 * u + lane];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            *reinterpret_cast<uint32_t*>(base + 4u * (i0 + 64u * u + lane)) = t[u];
+    }
+    if (whole < nwords) {
+        uint32_t t[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) t[u] = stage[whole + 64 * u + lane];
         // keeps the compiler from sinking a read into its store's branch
         asm volatile("" : : "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3]));
 #pragma unroll
         for (int u = 0; u < 4; u++)
-            if (i0 + 64 * u + lane < nwords) dst[i0 + 64 * u + lane] = t[u];
+            if (whole + 64 * u + lane < nwords)
+                *reinterpret_cast<uint32_t*>(base + 4u * (whole + 64u * u + lane)) = t[u];
     }
     wave_lds_sync();
 }
