@@ -23,13 +23,16 @@ namespace {
 
 constexpr uint32_t kDigitBits = 5;
 constexpr uint32_t kDigits = 1u << kDigitBits;
-// Digit counters, digit-major: (d, lane) at d*64 + lane, with 4 pad words per
-// 32 so that the raking scan reads 16-byte chunks without bank conflicts.
-constexpr uint32_t kCounterWords = kDigits * 64 + kDigits * 64 / 8;
+// Digit counters, digit-major: (d, lane) at d*68 + lane (4 pad words per
+// digit row, so that the raking scan's 16-byte reads spread over the banks).
+// The address is one multiply-add of the digit; the clearing loop writes
+// 2304 words (nine 16-byte stores per lane), past the 2176 used.
+constexpr uint32_t kRow = 68;
+constexpr uint32_t kCounterWords = 64 * 9 * 4;
+static_assert(kDigits * kRow <= kCounterWords, "counter rows fit the cleared region");
 
 __device__ __forceinline__ uint32_t counter_addr(uint32_t d, uint32_t lane) {
-    uint32_t f = d * 64 + lane;
-    return f + 4 * (f >> 5);
+    return d * kRow + lane;
 }
 
 // Padded blocked layout: position p of a block lives at p + 4*(p / ITEMS), so
@@ -299,14 +302,15 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
     uint32_t rank[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        uint32_t d = (kv[j] >> (16 + sh)) & (kDigits - 1);
+        const uint32_t d = __builtin_amdgcn_ubfe(kv[j], 16 + sh, kDigitBits);
         if (FULL || lane * ITEMS + j < nb) rank[j] = atomicAdd(&cnt[counter_addr(d, lane)], 1u);
         else rank[j] = 0u;
     }
     wave_lds_sync();
     {
-        // lane r scans flat entries [32r, 32r+32) stored at 36r..36r+31
-        uint4* row = reinterpret_cast<uint4*>(cnt + 36 * lane);
+        // lane r scans flat entries [32r, 32r+32) of (digit, lane) order:
+        // digit r/2, lanes 32*(r%2) .. 32*(r%2)+31, contiguous in its row
+        uint4* row = reinterpret_cast<uint4*>(cnt + (lane >> 1) * kRow + (lane & 1) * 32);
         uint32_t c[32];
 #pragma unroll
         for (int k = 0; k < 8; k++) {
@@ -334,7 +338,7 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
     // between them would make every read wait for the one before it.
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        uint32_t d = (kv[j] >> (16 + sh)) & (kDigits - 1);
+        const uint32_t d = __builtin_amdgcn_ubfe(kv[j], 16 + sh, kDigitBits);
         rank[j] += cnt[counter_addr(d, lane)];
     }
 #pragma unroll
