@@ -96,18 +96,33 @@ __device__ __forceinline__ void copy_body(const CopyArgs& a, uint32_t b, uint32_
     }
     const uint32_t* src = a.temp + (uint64_t)b * a.slot_words;
     uint32_t* dst = recs + off;
-    // up to 16 loads in flight per lane (4 KB per wave) before the stores
+    // 16 loads in flight per lane (4 KB per wave) before the stores; whole
+    // 1024-word steps run without per-word predicates, at 32-bit offsets
+    // from the scalar bases, and only the last step is predicated.
     constexpr int U = 16;
-    for (uint32_t k0 = 0; k0 < len; k0 += 64 * U) {
+    const uint8_t* sb8 = reinterpret_cast<const uint8_t*>(src);
+    uint8_t* db8 = reinterpret_cast<uint8_t*>(dst);
+    const uint32_t whole = len & ~(64u * U - 1u);
+    for (uint32_t k0 = 0; k0 < whole; k0 += 64 * U) {
+        uint32_t v[U];
+#pragma unroll
+        for (int i = 0; i < U; i++)
+            v[i] = __builtin_nontemporal_load(
+                reinterpret_cast<const uint32_t*>(sb8 + 4u * (k0 + 64u * i + lane)));
+#pragma unroll
+        for (int i = 0; i < U; i++)
+            *reinterpret_cast<uint32_t*>(db8 + 4u * (k0 + 64u * i + lane)) = v[i];
+    }
+    if (whole < len) {
         uint32_t v[U];
 #pragma unroll
         for (int i = 0; i < U; i++) {
-            const uint32_t k = k0 + 64 * i + lane;
+            const uint32_t k = whole + 64 * i + lane;
             v[i] = k < len ? __builtin_nontemporal_load(src + k) : 0u;
         }
 #pragma unroll
         for (int i = 0; i < U; i++) {
-            const uint32_t k = k0 + 64 * i + lane;
+            const uint32_t k = whole + 64 * i + lane;
             if (k < len) dst[k] = v[i];
         }
     }
