@@ -106,27 +106,45 @@ template <int ITEMS, bool FULL>
 __device__ __forceinline__ FieldCodes quantize_field(const float (&v)[ITEMS], uint32_t nb,
                                                      uint32_t lane, float inv, float twoeb,
                                                      float eb, uint32_t (&q)[ITEMS]) {
+    // Block minimum over the finite values.  +inf is the minimum's identity,
+    // so only NaN and -inf have to be skipped: a minimum that propagates NaN
+    // over the raw values ends up NaN or -inf in some lane exactly when the
+    // block holds one of them, and only then are values filtered one by one.
+    // The test is a class test (signalling NaN, quiet NaN, -inf): the
+    // compiler lowered the equivalent `m > -inf` under a wave vote to an
+    // unordered compare, which a NaN passes.
     float m = __builtin_inff();
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        bool ok = (FULL || lane * ITEMS + j < nb) && __builtin_isfinite(v[j]);
-        m = fminf(m, ok ? v[j] : __builtin_inff());
+    for (int j = 0; j < ITEMS; j++)
+        m = __builtin_elementwise_minimum(
+            m, (FULL || lane * ITEMS + j < nb) ? v[j] : __builtin_inff());
+    if (__any(__builtin_amdgcn_classf(m, 7))) {
+        m = __builtin_inff();
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            bool ok = (FULL || lane * ITEMS + j < nb) && __builtin_isfinite(v[j]);
+            m = fminf(m, ok ? v[j] : __builtin_inff());
+        }
     }
     m = wave_min_f32(m);
     const float lo = (m == __builtin_inff() || m == 0.0f) ? 0.0f : m;
-    bool good = true;
+    // Every error is below eb exactly when the largest one is.  The maximum
+    // propagates NaN (a non-finite value's error), which then fails the test
+    // like the value's own comparison would; it takes two errors per
+    // instruction where a per-value flag took a compare and a select.
+    float emax = 0.0f;
     float rmax = 0.0f;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const bool valid = FULL || lane * ITEMS + j < nb;
         const float r = __builtin_rintf((v[j] - lo) * inv);
         const float xr = __builtin_fmaf(r, twoeb, lo);
-        good = good & (!valid | (__builtin_fabsf(xr - v[j]) < eb));
+        emax = __builtin_elementwise_maximum(emax, valid ? __builtin_fabsf(xr - v[j]) : 0.0f);
         rmax = fmaxf(rmax, valid ? r : 0.0f);
         q[j] = valid ? (uint32_t)(r + r) : 0u;
     }
     uint32_t qmax = wave_max_u32(rmax <= kQMax ? (uint32_t)rmax : 0xFFFFFFFFu);
-    if (__all(good) && qmax <= 0xFFFFFFu) return {lo, qmax, true};
+    if (__all(emax < eb) && qmax <= 0xFFFFFFu) return {lo, qmax, true};
     // some value is an outlier: the quantizer's steps, value by value
     uint32_t mx = 0;
 #pragma unroll

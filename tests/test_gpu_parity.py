@@ -178,6 +178,43 @@ def test_quantizer_range_boundary(gpz, orc):
     check_case(gpz, orc, host, eb, B=B, KF=1, label="quantizer range boundary")
 
 
+def test_block_minimum_non_finite(gpz, orc):
+    """The block minimum lo (Sec. 4.1) is taken over finite values only.
+    Each block holds one arrangement of non-finite values in an otherwise
+    finite field: none, a single NaN of either sign (quiet and signalling),
+    a single -inf or +inf, all +inf, all NaN, -inf beside NaN, and a
+    negative NaN in the block's first or last position; the partial last
+    block holds one too.  A negative NaN is the smallest float under an
+    order-preserving integer key, so a minimum that let it through would
+    set lo to NaN."""
+    B = 1024
+    rng = np.random.default_rng(31)
+    bits = lambda u: np.array([u], np.uint32).view(np.float32)[0]
+    qnan, nqnan, nsnan = bits(0x7FC00000), bits(0xFFC00001), bits(0xFF800001)
+    cases = [
+        {}, {"r": qnan}, {"r": nqnan}, {"r": nsnan}, {"r": -np.inf}, {"r": np.inf},
+        {"all": np.inf}, {"all": nqnan}, {"r": -np.inf, "r2": qnan},
+        {0: nqnan}, {B - 1: nqnan}, {"r": nqnan},
+    ]
+    n = (len(cases) - 1) * B + 517
+    host = []
+    for f in range(5):
+        x = (rng.standard_normal(n) * 10 + 3).astype(np.float32)
+        for b in range(len(cases)):
+            c = cases[(b + 2 * f) % len(cases)]
+            lo, hi = b * B, min(n, (b + 1) * B)
+            for key, v in c.items():
+                if key == "all":
+                    x[lo:hi] = v
+                elif key in ("r", "r2"):
+                    x[lo + int(rng.integers(0, hi - lo))] = v
+                elif lo + key < hi:
+                    x[lo + key] = v
+        host.append(x)
+    for eb in (1e-3, 0.5):
+        check_case(gpz, orc, host, eb, KF=3, label=f"non-finite block minimum eb={eb}")
+
+
 def test_raw_fallback_and_constant(gpz, orc):
     rng = np.random.default_rng(6)
     host = [rng.random(4000).astype(np.float32) for _ in range(2)]
