@@ -108,6 +108,52 @@ def test_batch_matches_oracle(gpz, orc):
     b.close()
 
 
+@pytest.mark.parametrize("grid,tile", [(97, 3), (0, 1)])
+def test_batch_non_finite_blocks(gpz, orc, grid, tile):
+    """The batched encoders share the plain one's block minimum over finite
+    values (Sec. 4.1).  Jobs whose blocks each hold one arrangement of
+    non-finite values (a single NaN of either sign, -inf, +inf, all NaN, a
+    negative NaN in the first or last position) must give the oracle's
+    stream, in the persistent and the one-workgroup-per-block launches."""
+    from paper_2508_10305_amd.batch import default_config
+    bits = lambda u: np.array([u], np.uint32).view(np.float32)[0]
+    specials = [None, bits(0x7FC00000), bits(0xFFC00001), bits(0xFF800001), -np.inf, np.inf,
+                "all", 0, 1023]
+    rng = np.random.default_rng(41)
+    jobs = []
+    for n, F in [(9 * 1024, 6), (5 * 1024 + 300, 4), (2000, 3)]:
+        host = []
+        for f in range(F):
+            x = (rng.standard_normal(n) * 5 - 2).astype(np.float32)
+            for b in range(-(-n // 1024)):
+                lo, hi = b * 1024, min(n, (b + 1) * 1024)
+                c = specials[(b + f) % len(specials)]
+                if c is None:
+                    continue
+                if isinstance(c, str):
+                    x[lo:hi] = bits(0xFFC00001)
+                elif isinstance(c, int):
+                    if lo + c < hi:
+                        x[lo + c] = bits(0xFFC00001)
+                else:
+                    x[lo + int(rng.integers(0, hi - lo))] = c
+            host.append(x)
+        jobs.append((host, 1e-3))
+    cfg = default_config()
+    cfg.grid = grid
+    cfg.tile = tile
+    say(f"[case] batch non-finite blocks grid={grid} tile={tile}")
+    b, fields, outs, decs, ebs = build_batch(gpz, jobs, cfg)
+    b.compress()
+    sizes = b.sizes()
+    assert (b.errors() == 0).all()
+    for j, (host, eb) in enumerate(jobs):
+        ref, _ = orc.compress(host, eb)
+        got = outs[j][: int(sizes[j])].cpu().numpy()
+        assert got.size == ref.size and (got == ref).all(), f"job {j} differs from the oracle"
+    b.close()
+
+
 def test_graph_replays_with_eager_work_between(gpz):
     jobs = make_jobs(13, [50_000, 8_000, 120_000])
     ref = plain_results(gpz, jobs)
