@@ -310,7 +310,7 @@ def main():
 
 
 def bench_rd(args):
-    """Rate-distortion sweep (Sec. 2's analysis: bit rate against aggregate
+    """Rate-distortion sweep (Sec. 3.1's analysis: bit rate against aggregate
     PSNR) over the four synthetic workloads at their full sizes and relative
     bounds 1e-2 ... 1e-5, with compression ratio, outliers and GPU rates."""
     import torch

@@ -140,7 +140,7 @@ int gpz_bound_check(const float *const *h_orig, const float *const *h_recon,
 /* As gpz_bound_check, and also h_sum_sq_err[F] (nullable): the sum over
  * pairs whose difference is a number of (recon - orig)^2 in double, from
  * which the normalized RMSE of every field and the aggregate PSNR of the
- * rate-distortion analysis (Sec. 2) follow.  The summation order is not
+ * rate-distortion analysis (Sec. 3.1) follow.  The summation order is not
  * fixed: the sums may differ from a sequential sum in the last bits.
  * Synchronizes `stream`. */
 int gpz_error_stats(const float *const *h_orig, const float *const *h_recon,
@@ -211,7 +211,8 @@ typedef struct {
     uint32_t tile;       /* consecutive blocks taken per work-queue grab; default 1 */
     uint32_t use_graph;  /* 1: capture the kernel sequence once, then replay it */
     uint32_t max_jobs;   /* capacity for gpz_batch_rebind (0: the creation job count) */
-    uint64_t max_blocks; /* capacity in blocks over all jobs (0: at creation) */
+    uint64_t max_blocks; /* capacity in blocks over all jobs (0: at creation); at most
+                            2^30, and at most 2^26 when grid is 0 (GPZ_EINVAL beyond) */
 } gpz_batch_config;
 
 typedef struct gpz_batch gpz_batch;

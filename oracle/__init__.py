@@ -195,6 +195,120 @@ def compress(fields: Sequence[np.ndarray], eb, B: int = 1024, K: int = 3,
     return out[: nbytes.value].copy(), (perm[:n] if want_perm else None)
 
 
+# ---------------------------------------------------------------- block-parallel framing
+# Blocks are encoded independently (Sec. 4: the sort and the codes are local
+# to a block), so the stream of a large snapshot is the stream framing
+# (header, superblock table, eb table, length table) around the records of
+# its blocks in order.  These helpers run the oracle on block-aligned chunks,
+# one call per host thread (ctypes releases the GIL), and frame the chunks'
+# records into the one stream the whole call would write.  Only the framing
+# is done here; every record comes from oracle_compress / oracle_decompress.
+
+_MAGIC, _HEADER, _SUPER = 0x315A5047, 8, 64
+
+
+def _threads(threads: Optional[int]) -> int:
+    if threads:
+        return threads
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _split(stream: np.ndarray):
+    """(header words, eb bits, record lengths, record words) of a stream."""
+    w = np.ascontiguousarray(stream, dtype=np.uint8).view(np.uint32)
+    nb = int(w[7])
+    ns = (nb + _SUPER - 1) // _SUPER
+    F = int(w[4])
+    eb = w[_HEADER + 2 * ns: _HEADER + 2 * ns + F]
+    lens = w[_HEADER + 2 * ns + F: _HEADER + 2 * ns + F + nb]
+    return w[:_HEADER], eb, lens, w[_HEADER + 2 * ns + F + nb:]
+
+
+def _frame(n: int, F: int, B: int, K: int, KF: int, eb_bits: np.ndarray, lens: np.ndarray,
+           records: np.ndarray) -> np.ndarray:
+    nb = lens.size
+    ns = (nb + _SUPER - 1) // _SUPER
+    offs = np.concatenate([[0], np.cumsum(lens.astype(np.uint64))[:-1]]).astype(np.uint64) \
+        if nb else np.zeros(0, np.uint64)
+    sup = np.zeros(2 * ns, np.uint32)
+    sup[0::2] = (offs[::_SUPER] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    sup[1::2] = (offs[::_SUPER] >> np.uint64(32)).astype(np.uint32)
+    hdr = np.array([_MAGIC, 1, n & 0xFFFFFFFF, n >> 32, F, B, K | (KF << 8), nb], np.uint32)
+    return np.concatenate([hdr, sup, eb_bits.astype(np.uint32), lens.astype(np.uint32),
+                           records.astype(np.uint32)]).view(np.uint8)
+
+
+def compress_parallel(fields: Sequence[np.ndarray], eb, B: int = 1024, K: int = 3,
+                      KF: Optional[int] = None, threads: Optional[int] = None,
+                      want_perm: bool = False):
+    """(stream, perm or None) as compress() returns them, computed chunk by
+    chunk on host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    fields = [_f32(f) for f in fields]
+    F = len(fields)
+    n = fields[0].size
+    KF = min(F, 3) if KF is None else KF
+    nb = (n + B - 1) // B
+    T = _threads(threads)
+    per = max(1, -(-nb // (4 * T)))  # blocks per chunk: about four chunks per thread
+    chunks = [(b0 * B, min(n, (b0 + per) * B)) for b0 in range(0, nb, per)]
+
+    perm = np.zeros(n, np.uint32) if want_perm else None
+
+    def one(c):
+        s, pc = compress([f[c[0]:c[1]] for f in fields], eb, B=B, K=K, KF=KF,
+                         want_perm=want_perm)
+        if want_perm:
+            perm[c[0]:c[1]] = pc + np.uint32(c[0])  # chunk-relative input indices
+        return _split(s)
+    if not chunks:
+        return compress(fields, eb, B=B, K=K, KF=KF, want_perm=want_perm)
+    with ThreadPoolExecutor(T) as ex:
+        parts = list(ex.map(one, chunks))
+    lens = np.concatenate([p[2] for p in parts])
+    recs = np.concatenate([p[3] for p in parts])
+    return _frame(n, F, B, K, KF, parts[0][1], lens, recs), perm
+
+
+def decompress_parallel(stream: np.ndarray, n: int, F: int,
+                        threads: Optional[int] = None) -> List[np.ndarray]:
+    """What decompress() returns, computed chunk by chunk on host threads:
+    each chunk of blocks is framed as a stream of its own and decoded by the
+    oracle.  The whole stream's header and tables are checked first."""
+    from concurrent.futures import ThreadPoolExecutor
+    s = np.ascontiguousarray(stream, dtype=np.uint8)
+    info = inspect(s)
+    if info["n"] != n or info["F"] != F or info["bytes"] != s.size:
+        raise OracleError(ECORRUPT, "decompress_parallel")
+    hdr, eb_bits, lens, recs = _split(s)
+    B, K, KF, nb = info["B"], info["K"], info["KF"], info["nblocks"]
+    offs = np.concatenate([[0], np.cumsum(lens.astype(np.int64))]).astype(np.int64)
+    w = s.view(np.uint32)
+    sup = w[_HEADER: _HEADER + 2 * ((nb + _SUPER - 1) // _SUPER)].astype(np.uint64)
+    if nb and not ((sup[0::2] | (sup[1::2] << np.uint64(32))) == offs[:-1:_SUPER]).all():
+        raise OracleError(ECORRUPT, "decompress_parallel")
+    outs = [np.zeros(n, np.float32) for _ in range(F)]
+    T = _threads(threads)
+    per = max(1, -(-nb // (4 * T)))
+    ranges = [(b0, min(nb, b0 + per)) for b0 in range(0, nb, per)]
+
+    def one(r):
+        b0, b1 = r
+        lo, hi = b0 * B, min(n, b1 * B)
+        sub = _frame(hi - lo, F, B, K, KF, eb_bits, lens[b0:b1], recs[offs[b0]:offs[b1]])
+        part = decompress(sub, hi - lo, F)
+        for f in range(F):
+            outs[f][lo:hi] = part[f]
+    if not ranges:
+        return decompress(s, n, F)
+    with ThreadPoolExecutor(T) as ex:
+        list(ex.map(one, ranges))
+    return outs
+
+
 def encode_block(fields: Sequence[np.ndarray], eb, K: int = 3, KF: Optional[int] = None):
     """Record words of one block (all of ``fields``), and its permutation."""
     fields = [_f32(f) for f in fields]

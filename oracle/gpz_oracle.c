@@ -747,7 +747,7 @@ int oracle_field_range(const float *const *fields, uint64_t n, uint32_t F, float
     return OR_OK;
 }
 
-/* Rate-distortion statistics of a reconstruction (Sec. 2): per field the sum
+/* Rate-distortion statistics of a reconstruction (Sec. 3.1): per field the sum
  * of squared differences recon[f][j] - orig[f][perm[j]] in double, summed in
  * position order over the pairs whose difference is a number (perm entries
  * outside [0, n) are skipped); then the normalized RMSE of every field,

@@ -310,7 +310,7 @@ def bound_check(orig: Sequence, recon: Sequence, eb, perm=None, stream=None
 
 
 def error_stats(orig: Sequence, recon: Sequence, eb, perm=None, stream=None) -> dict:
-    """Bound check plus rate-distortion figures (Sec. 2): per-field violation
+    """Bound check plus rate-distortion figures (Sec. 3.1): per-field violation
     counts, maximum and summed squared errors, normalized RMSE over each
     original field's range, and the aggregate PSNR in dB."""
     F = len(orig)

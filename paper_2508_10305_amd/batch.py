@@ -120,6 +120,17 @@ class Batch:
         """Stream sizes as a device tensor view (uint64, one per job)."""
         return device_view(_lib().gpz_batch_sizes(self.handle), self.njobs, "<i8")
 
+    def capacity_views(self):
+        """(sizes, errors): device tensor views of the batch's whole size and
+        error tables (int64 / int32, max_jobs entries each).  The tables stay
+        at the same address for the life of the batch, so the views are made
+        once and sliced by the caller."""
+        if getattr(self, "_views", None) is None:
+            cap = max(1, self.config.max_jobs or self.njobs)
+            self._views = (device_view(_lib().gpz_batch_sizes(self.handle), cap, "<i8"),
+                           device_view(_lib().gpz_batch_errors(self.handle), cap, "<i4"))
+        return self._views
+
     def sizes(self) -> np.ndarray:
         """Stream size per job (synchronizes the device)."""
         import torch

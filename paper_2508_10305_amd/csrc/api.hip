@@ -275,19 +275,8 @@ static int decompress_impl(const void* d_in, uint64_t in_bytes, float* const* h_
     const uint64_t pre = prefix_words(n, F, B);
     if (nb > ((uint64_t)1 << 26)) return GPZ_EINVAL;
     if (in_bytes < 4 * pre || (exact && in_bytes % 4 != 0)) return GPZ_ECORRUPT;
-    if (nb == 0) {
-        // nothing to decode; the stream is the header and the eb table
-        if (exact && in_bytes != 4 * pre) return GPZ_ECORRUPT;
-        std::vector<uint32_t> h(pre);
-        if (hipMemcpyAsync(h.data(), d_in, 4 * pre, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return GPZ_EDEVICE;
-        for (uint32_t f = 0; f < F; f++) {
-            float e;
-            memcpy(&e, &h[kHeaderWords + f], 4);
-            if (!eb_valid(e)) return GPZ_ECORRUPT;
-        }
-    }
+    // (no blocks: the decode launch checks the header and eb table on the
+    // device, so this path never waits for the stream either)
     DecodeArgs da{};
     da.in = static_cast<const uint32_t*>(d_in);
     da.in_words = in_bytes / 4;

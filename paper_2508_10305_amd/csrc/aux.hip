@@ -291,12 +291,16 @@ __global__ __launch_bounds__(256) void stream_stats_kernel(StatsArgs a) {
     uint32_t len = 0, nn = 0;
     const uint32_t* rec = a.in + a.prefix;
     if (live) {
+        // superblock entry checked before use, lengths summed in 64 bits (at
+        // most 63 of them): no sum wraps, an accepted record lies inside the
+        // record area
         const uint32_t sb = b / kSuper;
-        off = (uint64_t)sup[2 * sb] | ((uint64_t)sup[2 * sb + 1] << 32);
+        const uint64_t sup_off = (uint64_t)sup[2 * sb] | ((uint64_t)sup[2 * sb + 1] << 32);
+        off = sup_off;
         for (uint32_t k = sb * kSuper; k < b; k++) off += lt[k];
         len = lt[b];
         nn = (uint32_t)((uint64_t)(b + 1) * a.B <= a.n ? a.B : a.n - (uint64_t)b * a.B);
-        bad = len < 1 || off + len > rec_total;
+        bad = len < 1 || sup_off > rec_total || off > rec_total || (uint64_t)len > rec_total - off;
         if (!bad) {
             rec += off;
             raw = (rec[0] & 3u) == 1u;

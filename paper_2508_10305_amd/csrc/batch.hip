@@ -336,7 +336,10 @@ int gpz_batch_create(gpz_batch** out, const gpz_job* jobs, uint32_t njobs, const
     // every job adds at most one partially filled superblock
     b->max_super = c.max_blocks ? (c.max_blocks / kSuper + b->max_jobs) : nsuper_all;
     if (b->max_jobs < njobs || b->max_blocks < nblocks_all || b->max_super < nsuper_all ||
-        b->max_blocks > ((uint64_t)1 << 30) || b->max_jobs == 0) {
+        b->max_blocks > ((uint64_t)1 << 30) || b->max_jobs == 0 ||
+        (c.grid == 0 && b->max_blocks > ((uint64_t)1 << 26))) {
+        // direct launches run one 64-lane workgroup per block of the
+        // capacity: the dispatch size (64 * blocks) must fit 32 bits
         delete b;
         return GPZ_EINVAL;
     }

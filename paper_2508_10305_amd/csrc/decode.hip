@@ -75,6 +75,33 @@ __device__ __forceinline__ uint32_t extract(const uint32_t* __restrict__ words, 
 
 __device__ __forceinline__ uint32_t low_mask(uint32_t w) { return w >= 32u ? ~0u : ((1u << w) - 1u); }
 
+// Sum over the wave of one 64-bit value per lane (every lane gets it).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Whether the stream's header or eb table does not describe the stream the
+// caller asked for (lane k < 8 checks header word k, every lane a share of
+// the eb table).  Per-lane result.
+__device__ __forceinline__ bool header_bad(const DecodeArgs& a, uint32_t lane) {
+    bool bad = false;
+    const uint32_t* ebt = a.in + kHeaderWords + 2 * nsuper_of(a.nblocks);
+    for (uint32_t f = lane; f < a.F; f += 64)
+        if (!eb_ok(u2f(ebt[f]))) bad = true;
+    if (lane < kHeaderWords) {
+        const uint32_t expect[kHeaderWords] = {kMagic, kVersion, (uint32_t)(a.n & 0xFFFFFFFFu),
+                                               (uint32_t)(a.n >> 32), a.F, a.B,
+                                               a.K | (a.KF << 8), a.nblocks};
+        uint32_t want = expect[0];
+#pragma unroll
+        for (uint32_t k = 1; k < kHeaderWords; k++) want = lane == k ? expect[k] : want;
+        if (a.in[lane] != want) bad = true;
+    }
+    return bad;
+}
+
 template <int ITEMS>
 struct DecodeSmem {
     static constexpr uint32_t B = 64 * ITEMS;
@@ -115,32 +142,25 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
     const uint32_t* recs = a.in + a.prefix;
     const uint64_t rec_total = a.in_words - a.prefix;
 
-    // ---- locate the record: superblock offset + lengths before it
+    // ---- locate the record: superblock offset + lengths before it.  The
+    // superblock entry is checked against the record area before anything is
+    // added to it, and the lengths are summed in 64 bits, so no sum can wrap
+    // and every accepted [off, off + len) lies inside the record area.
     const uint32_t sb = b / kSuper;
     const uint32_t first = sb * kSuper;
-    uint32_t mine = (first + lane < b) ? lens[first + lane] : 0u;
-    uint64_t off = ((uint64_t)sup[2 * sb] | ((uint64_t)sup[2 * sb + 1] << 32)) + wave_sum_u32(mine);
+    const uint64_t sup_off = (uint64_t)sup[2 * sb] | ((uint64_t)sup[2 * sb + 1] << 32);
+    const uint64_t mine = (first + lane < b) ? (uint64_t)lens[first + lane] : 0ull;
+    const uint64_t off = sup_off + wave_sum_u64(mine);
     const uint32_t len = lens[b];
-    bool bad = off + len > rec_total;
+    bool bad = sup_off > rec_total || off > rec_total || (uint64_t)len > rec_total - off;
     if (b == 0 && (sup[0] | sup[1]) != 0u) bad = true;
     if (a.exact && b + 1 == a.nblocks && off + len != rec_total) bad = true;
-    for (uint32_t f = lane; f < F; f += 64)
-        if (!eb_ok(u2f(ebt[f]))) bad = true;
-    if (lane < kHeaderWords) {
-        // the header must describe the stream the caller asked for
-        const uint32_t expect[kHeaderWords] = {kMagic, kVersion, (uint32_t)(a.n & 0xFFFFFFFFu),
-                                               (uint32_t)(a.n >> 32), F, a.B, K | (KF << 8),
-                                               a.nblocks};
-        uint32_t want = expect[0];
-#pragma unroll
-        for (uint32_t k = 1; k < kHeaderWords; k++) want = lane == k ? expect[k] : want;
-        if (a.in[lane] != want) bad = true;
-    }
+    if (header_bad(a, lane)) bad = true;
     if (b == first && sb > 0) {
         // consistency of this superblock's offset with the previous one
-        uint32_t pl = lens[first - kSuper + lane];
-        uint64_t prev = ((uint64_t)sup[2 * sb - 2] | ((uint64_t)sup[2 * sb - 1] << 32));
-        if (prev + wave_sum_u32(pl) != off) bad = true;
+        const uint64_t pl = lens[first - kSuper + lane];
+        const uint64_t prev = ((uint64_t)sup[2 * sb - 2] | ((uint64_t)sup[2 * sb - 1] << 32));
+        if (prev > rec_total || prev + wave_sum_u64(pl) != off) bad = true;
     }
     if (__any(bad)) {
         if (lane == 0) *a.err = 1u;
@@ -401,6 +421,16 @@ __global__ __launch_bounds__(64) void decode_batch_direct(const DecodeArgs* __re
     decode_block<ITEMS>(jobs[j], g - prefix[j], sm);
 }
 
+// A stream of a snapshot with no particles holds only its header, its
+// superblock table (empty) and its eb table: one wave checks them, so the
+// caller needs no host copy of the stream.
+__global__ __launch_bounds__(64) void check_empty_stream(DecodeArgs a) {
+    const uint32_t lane = threadIdx.x;
+    bool bad = header_bad(a, lane);
+    if (a.exact && a.in_words != a.prefix) bad = true;
+    if (__any(bad) && lane == 0) *a.err = 1u;
+}
+
 }  // namespace
 
 hipError_t launch_decode_batch(const DecodeArgs* jobs, const BatchLaunch* L,
@@ -429,7 +459,10 @@ hipError_t launch_decode_batch(const DecodeArgs* jobs, const BatchLaunch* L,
 }
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t s) {
-    if (a.nblocks == 0) return hipSuccess;
+    if (a.nblocks == 0) {
+        hipLaunchKernelGGL(check_empty_stream, dim3(1), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
     dim3 grid(a.nblocks), block(64);
     switch (a.B) {
         case 256: hipLaunchKernelGGL(decode_blocks<4>, grid, block, 0, s, a); break;

@@ -102,6 +102,8 @@ class Request:
     t_admit: float = 0.0
     t_done: float = 0.0
     batch: int = -1
+    nbytes: int = -1         # compress: stream size the library reported
+    status: int = -1         # decompress: the decoder's error flag (0: the stream was valid)
 
 
 @dataclass
@@ -114,8 +116,10 @@ class _Slot:
     busy: bool = False
     event: object = None
     reqs: list = field(default_factory=list)
-    sizes: object = None
+    sizes: object = None     # device scalars of a plain launch
     err: object = None
+    h_sizes: object = None   # pinned host copies of the launch's sizes / error flags,
+    h_err: object = None     # queued on the slot's stream before its completion event
 
 
 class Server:
@@ -148,6 +152,10 @@ class Server:
             sl.batch_d.decompress(stream=sl.stream)
             sl.sizes = torch.zeros(1, dtype=torch.int64, device=device)
             sl.err = torch.zeros(1, dtype=torch.int32, device=device)
+            sl.h_sizes = torch.zeros(max_jobs, dtype=torch.int64, pin_memory=True)
+            sl.h_err = torch.zeros(max_jobs, dtype=torch.int32, pin_memory=True)
+            sl.batch_c.capacity_views()
+            sl.batch_d.capacity_views()
             self.slots.append(sl)
         torch.cuda.synchronize()
         self.batches = 0
@@ -209,12 +217,16 @@ class Server:
                                     dec=[r.out for r in dec], workspace=ws, stream=slot.stream)
             if comp:
                 slot.batch_c.compress(stream=slot.stream)
+                slot.h_sizes[: len(comp)].copy_(slot.batch_c.capacity_views()[0][: len(comp)],
+                                                non_blocking=True)
             if dec:
                 slot.batch_d.decompress(stream=slot.stream)
+                slot.h_err[: len(dec)].copy_(slot.batch_d.capacity_views()[1][: len(dec)],
+                                             non_blocking=True)
             slot.event = torch.cuda.Event()
             slot.event.record(slot.stream)
         slot.busy = True
-        slot.reqs = reqs
+        slot.reqs = comp + dec  # the order of the size and error copies
         for r in reqs:
             r.batch = self.batches
         self.batches += 1
@@ -234,12 +246,16 @@ class Server:
                 ctypes.byref(self.p), r.out.data_ptr(), r.out.numel(), slot.sizes.data_ptr(), None,
                 r.ws.data_ptr(), r.ws.numel(), s)
             _check(rc, "gpz_compress_async")
+            with torch.cuda.stream(slot.stream):
+                slot.h_sizes[:1].copy_(slot.sizes, non_blocking=True)
         else:
             ptrs = _ptr_array(r.out)
             rc = _lib().gpz_decompress_async(r.stream.data_ptr(), r.stream.numel(),
                                              ctypes.cast(ptrs, ctypes.c_void_p), r.n, r.F,
                                              ctypes.byref(self.p), slot.err.data_ptr(), s)
             _check(rc, "gpz_decompress_async")
+            with torch.cuda.stream(slot.stream):
+                slot.h_err[:1].copy_(slot.err, non_blocking=True)
         ev = torch.cuda.Event()
         ev.record(slot.stream)
         slot.event = ev
@@ -290,8 +306,18 @@ class Server:
             # completions
             for slot in self.slots:
                 if slot.busy and slot.event.query():
+                    # the launch's sizes and error flags reached pinned memory
+                    # before its completion event: compress requests take their
+                    # sizes in order, decompress requests their error flags
+                    ic = idd = 0
                     for r in slot.reqs:
                         r.t_done = now
+                        if r.op == "compress":
+                            r.nbytes = int(slot.h_sizes[ic])
+                            ic += 1
+                        else:
+                            r.status = int(slot.h_err[idd])
+                            idd += 1
                         if on_done is not None:
                             on_done(r)
                         self._release(r)
@@ -352,6 +378,10 @@ class Server:
                         admitted[:] = [r for r in admitted if id(r) not in ids]
                         last_progress = now
         wall = time.perf_counter() - t0
+        failed = [r for r in done if r.op == "decompress" and r.status != 0]
+        if failed:
+            raise RuntimeError(f"{len(failed)} decompression requests reported a malformed "
+                               f"stream (first: request {failed[0].rid})")
         lat = np.array([r.t_done - r.t * time_scale for r in done]) * 1e3
         nbytes = sum(4 * r.n * r.F for r in done)
         first = min(r.t for r in requests) * time_scale

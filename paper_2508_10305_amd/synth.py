@@ -18,6 +18,8 @@ distributions and storage order instead:
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import List
 
 import numpy as np
@@ -28,6 +30,28 @@ CHUNK = 1 << 22  # particles per generator chunk
 def _chunks(n: int):
     for start in range(0, n, CHUNK):
         yield start, min(CHUNK, n - start)
+
+
+def _workers() -> int:
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return max(1, min(16, cores))
+
+
+def _run_chunks(body, n: int):
+    """Calls body(ci, start, count) for every chunk, on a pool of host
+    threads.  Each chunk draws from its own spawned stream and writes its own
+    slice of the outputs, so the arrays do not depend on the thread count or
+    on the order in which chunks finish."""
+    chunks = list(enumerate(_chunks(n)))
+    if len(chunks) <= 1:
+        for ci, (s, m) in chunks:
+            body(ci, s, m)
+        return
+    with ThreadPoolExecutor(min(_workers(), len(chunks))) as ex:
+        list(ex.map(lambda c: body(c[0], *c[1]), chunks))
 
 
 def _streams(seed: int, count: int):
@@ -46,7 +70,8 @@ def clusters(n: int = 1_000_000, seed: int = 0, n_clusters: int = 64, sigma: flo
     rs = _streams(seed, nch)
     centres = rs[0].random((n_clusters, 3))
     out = [np.empty(n, np.float32) for _ in range(3 + extra_fields)]
-    for ci, (s, m) in enumerate(_chunks(n)):
+
+    def body(ci, s, m):
         r = rs[ci + 1]
         lab = r.integers(0, n_clusters, m)
         bg = r.random(m) < background
@@ -59,6 +84,7 @@ def clusters(n: int = 1_000_000, seed: int = 0, n_clusters: int = 64, sigma: flo
             out[a][s:s + m] = p32[:, a]
         for e in range(extra_fields):
             out[3 + e][s:s + m] = r.standard_normal(m).astype(np.float32)
+    _run_chunks(body, n)
     return out
 
 
@@ -74,7 +100,8 @@ def cosmology(n: int = 64_000_000, seed: int = 1, box: float = 256.0, n_halos: i
     sig = np.exp(rs[0].uniform(np.log(0.1), np.log(2.0), n_halos))
     bulk = rs[0].standard_normal((n_halos, 3)) * vsig
     out = [np.empty(n, np.float32) for _ in range(6)]
-    for ci, (s, m) in enumerate(_chunks(n)):
+
+    def body(ci, s, m):
         r = rs[ci + 1]
         lab = r.integers(0, n_halos, m)
         bg = r.random(m) < background
@@ -88,6 +115,7 @@ def cosmology(n: int = 64_000_000, seed: int = 1, box: float = 256.0, n_halos: i
         for a in range(3):
             out[a][s:s + m] = p32[:, a]
             out[3 + a][s:s + m] = v[:, a].astype(np.float32)
+    _run_chunks(body, n)
     return out
 
 
@@ -103,7 +131,8 @@ def md(cells: int = 200, seed: int = 2, a: float = 1.0, jitter: float = 0.05,
     nch = (n + CHUNK - 1) // CHUNK
     rs = _streams(seed, nch)
     out = [np.empty(n, np.float32) for _ in range(6)]
-    for ci, (s, m) in enumerate(_chunks(n)):
+
+    def body(ci, s, m):
         r = rs[ci + 1]
         i = np.arange(s, s + m, dtype=np.int64)
         b = i % 4
@@ -116,6 +145,7 @@ def md(cells: int = 200, seed: int = 2, a: float = 1.0, jitter: float = 0.05,
         for k in range(3):
             out[k][s:s + m] = p[:, k].astype(np.float32)
             out[3 + k][s:s + m] = v[:, k].astype(np.float32)
+    _run_chunks(body, n)
     return out
 
 
@@ -146,7 +176,8 @@ def lidar(n: int = 100_000_000, seed: int = 3, extent: float = 10_000.0, octaves
     # lattice values are drawn once per octave and reused for every chunk
     lat_states = [r.bit_generator.state for r in lat_rngs]
     out = [np.empty(n, np.float32) for _ in range(3)]
-    for ci, (s, m) in enumerate(_chunks(n)):
+
+    def body(ci, s, m):
         r = rs[ci + 1]
         x = r.random(m) * extent
         y = r.random(m) * extent
@@ -159,26 +190,8 @@ def lidar(n: int = 100_000_000, seed: int = 3, extent: float = 10_000.0, octaves
         out[0][s:s + m] = x.astype(np.float32)
         out[1][s:s + m] = y.astype(np.float32)
         out[2][s:s + m] = z.astype(np.float32)
+    _run_chunks(body, n)
     return out
-
-
-def batch_snapshots(count: int = 256, seed: int = 4, n_min: int = 10_000, n_max: int = 8_000_000,
-                    scale: float = 1.0):
-    """Snapshots of the batched form: particle counts log-uniform in
-    [n_min, n_max] (times ``scale``), 3-6 fields, cluster counts uniform in
-    [8, 1024], absolute bounds log-uniform in [1e-5, 1e-2].  Positions as in
-    ``clusters``; fields beyond the third are standard normal.  Yields
-    (fields, eb) pairs lazily."""
-    r = np.random.Generator(np.random.PCG64(seed))
-    ns = np.floor(np.exp(r.uniform(np.log(n_min), np.log(n_max), count)) * scale).astype(np.int64)
-    ns = np.maximum(ns, 1)
-    Fs = r.integers(3, 7, count)
-    ks = r.integers(8, 1025, count)
-    ebs = np.exp(r.uniform(np.log(1e-5), np.log(1e-2), count)).astype(np.float32)
-    seeds = r.integers(0, 2 ** 31, count)
-    for i in range(count):
-        f = clusters(int(ns[i]), int(seeds[i]), n_clusters=int(ks[i]), extra_fields=int(Fs[i]) - 3)
-        yield f, float(ebs[i])
 
 
 def request_stream(count: int = 20_000, seed: int = 5, rate: float = 2000.0, n_min: int = 100_000,
@@ -239,8 +252,10 @@ def clusters_device(n: int, seed: int, n_clusters: int = 64, sigma: float = 0.01
 
 
 def batch_specs(count: int = 256, seed: int = 4, n_min: int = 10_000, n_max: int = 8_000_000):
-    """Shapes of the batched-form snapshots (see batch_snapshots): list of
-    dicts with n, fields, clusters, eb, seed."""
+    """Shapes of the batched-form snapshots: particle counts log-uniform in
+    [n_min, n_max], 3-6 fields, cluster counts uniform in [8, 1024], absolute
+    bounds log-uniform in [1e-5, 1e-2].  List of dicts with n, fields,
+    clusters, eb, seed (the snapshot's generator seed)."""
     r = np.random.Generator(np.random.PCG64(seed))
     ns = np.maximum(1, np.floor(np.exp(r.uniform(np.log(n_min), np.log(n_max), count)))).astype(np.int64)
     Fs = r.integers(3, 7, count)

@@ -1,6 +1,7 @@
 """Batched form: every job of a batch must produce exactly the stream (and
-decompressed floats) of the plain per-snapshot path, with or without graph
-capture, on every graph replay, and after rebinding to new jobs."""
+decompressed floats) the CPU oracle computes for that snapshot alone, with or
+without graph capture, on every graph replay, and after rebinding to new
+jobs."""
 import sys
 
 import numpy as np
@@ -38,14 +39,16 @@ def make_jobs(seed, sizes, fields_per_job=None):
     return jobs
 
 
-def plain_results(gpz, jobs):
+def oracle_results(orc, jobs):
+    """Each job's stream and decoded fields from the CPU oracle: the batched
+    form is compared with what the method computes (Sec. 4.1-4.4, and the
+    reverse of Sec. 3.2), not with another GPU path."""
     ref = []
     for host, eb in jobs:
         n = host[0].size
-        dev = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in host]
-        s, _ = gpz.compress(dev, eb)
-        out = gpz.decompress(s, n, len(host))
-        ref.append((s.cpu().numpy(), [o.cpu().numpy() for o in out]))
+        s, _ = orc.compress(host, eb)
+        out = orc.decompress(s, n, len(host))
+        ref.append((s, out))
     return ref
 
 
@@ -78,13 +81,13 @@ def check_batch(b, outs, decs, ref, label):
 
 @pytest.mark.parametrize("use_graph", [0, 1])
 @pytest.mark.parametrize("grid,tile", [(97, 1), (97, 3), (0, 1)])
-def test_batch_equals_plain(gpz, use_graph, grid, tile):
+def test_batch_equals_plain(gpz, orc, use_graph, grid, tile):
     """grid 97: an odd persistent grid, blocks shared unevenly between waves;
     grid 0: one workgroup per block."""
     from paper_2508_10305_amd.batch import default_config
     sizes = [1, 1023, 1024, 1025, 5000, 0, 70_000, 200_001, 64 * 1024 + 7, 3]
     jobs = make_jobs(7, sizes)
-    ref = plain_results(gpz, jobs)
+    ref = oracle_results(orc, jobs)
     cfg = default_config()
     cfg.use_graph = use_graph
     cfg.tile = tile
@@ -98,13 +101,13 @@ def test_batch_equals_plain(gpz, use_graph, grid, tile):
 
 
 def test_batch_matches_oracle(gpz, orc):
+    """Batched compression and decompression, each job against the oracle:
+    stream bytes and size, then decoded bits, with no error flag."""
     jobs = make_jobs(11, [3000, 10_000, 1024 * 5], fields_per_job=[3, 5, 6])
     b, fields, outs, decs, ebs = build_batch(gpz, jobs)
     b.compress()
-    sizes = b.sizes()
-    for j, (host, eb) in enumerate(jobs):
-        ref, _ = orc.compress(host, eb)
-        assert (outs[j][: int(sizes[j])].cpu().numpy() == ref).all()
+    b.decompress()
+    check_batch(b, outs, decs, oracle_results(orc, jobs), "oracle")
     b.close()
 
 
@@ -154,9 +157,9 @@ def test_batch_non_finite_blocks(gpz, orc, grid, tile):
     b.close()
 
 
-def test_graph_replays_with_eager_work_between(gpz):
+def test_graph_replays_with_eager_work_between(gpz, orc):
     jobs = make_jobs(13, [50_000, 8_000, 120_000])
-    ref = plain_results(gpz, jobs)
+    ref = oracle_results(orc, jobs)
     b, fields, outs, decs, ebs = build_batch(gpz, jobs)
     for rep in range(4):
         for o in outs:
@@ -177,11 +180,11 @@ def test_graph_replays_with_eager_work_between(gpz):
 
 
 @pytest.mark.parametrize("grid", [2048, 0])
-def test_rebind_keeps_graphs_valid(gpz, grid):
+def test_rebind_keeps_graphs_valid(gpz, orc, grid):
     from paper_2508_10305_amd.batch import default_config
     jobs_a = make_jobs(17, [30_000, 2_000, 9_000])
     jobs_b = make_jobs(19, [100_000, 1_500])
-    ref_b = plain_results(gpz, jobs_b)
+    ref_b = oracle_results(orc, jobs_b)
     total_blocks = sum((h[0].size + 1023) // 1024 for h, _ in jobs_a + jobs_b)
     cfg = default_config()
     cfg.grid = grid
@@ -207,7 +210,7 @@ def test_rebind_keeps_graphs_valid(gpz, grid):
     b.close()
 
 
-def test_rebinds_back_to_back_on_one_stream(gpz):
+def test_rebinds_back_to_back_on_one_stream(gpz, orc):
     """Rebinds queue their table upload on the caller's stream and return
     without waiting for it: three job lists bound, compressed and decompressed
     in a row on one side stream, with no host synchronization of our own,
@@ -215,7 +218,7 @@ def test_rebinds_back_to_back_on_one_stream(gpz):
     from paper_2508_10305_amd.batch import Batch, default_config
     lists = [make_jobs(31 + k, sizes) for k, sizes in
              enumerate([[40_000, 3_000], [1_025, 90_000, 7], [64 * 1024, 12_345, 2_048]])]
-    refs = [plain_results(gpz, jobs) for jobs in lists]
+    refs = [oracle_results(orc, jobs) for jobs in lists]
     cfg = default_config()
     b = Batch.empty(8, 256, config=cfg)
     s = torch.cuda.Stream()
@@ -270,20 +273,17 @@ def test_batch_reports_corrupt_stream(gpz):
 
 @pytest.mark.parametrize("B", [256, 2048])
 @pytest.mark.parametrize("grid", [300, 0])
-def test_batch_other_block_sizes(gpz, B, grid):
-    """Batched streams equal plain ones at other block sizes too (full and
-    partial blocks, persistent and direct launches)."""
+def test_batch_other_block_sizes(gpz, orc, B, grid):
+    """Batched streams and decoded fields equal the oracle's at other block
+    sizes too (full and partial blocks, persistent and direct launches)."""
     from paper_2508_10305_amd.batch import default_config
     jobs = make_jobs(29 + B, [B - 1, B, 3 * B + 5, 40_000, 0, 7])
     p = gpz.params(3, block_size=B)
     ref = []
     for host, eb in jobs:
         n = host[0].size
-        dev = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in host]
-        pp = gpz.params(len(host), block_size=B)
-        s, _ = gpz.compress(dev, eb, block_size=B, key_fields=pp.key_fields)
-        out = gpz.decompress(s, n, len(host))
-        ref.append((s.cpu().numpy(), [o.cpu().numpy() for o in out]))
+        s, _ = orc.compress(host, eb, B=B)
+        ref.append((s, orc.decompress(s, n, len(host))))
     cfg = default_config()
     cfg.grid = grid
     say(f"[case] batch B={B} grid={grid}")

@@ -1,5 +1,7 @@
 """Serving form: continuous batching must give every request exactly the
-result it gets alone, and admission must respect the HBM budget."""
+result the CPU oracle computes for it alone (stream bytes and size of a
+compression, decoded bits and a clean status of a decompression), and
+admission must respect the HBM budget."""
 import sys
 
 import numpy as np
@@ -25,38 +27,43 @@ def setup():
     return gpz, serve, reqs
 
 
-def alone(gpz, r):
+def oracle_result(orc, r):
+    """What the request computes, by the CPU oracle on host copies of its
+    input: the stream of its slice (compress) or the decoded template
+    (decompress)."""
     if r.op == "compress":
-        s, _ = gpz.compress(list(r.fields), r.eb)
-        return s.cpu().numpy()
-    out = gpz.decompress(r.stream, r.n, r.F)
-    return [o.cpu().numpy() for o in out]
+        host = [f.cpu().numpy() for f in r.fields]
+        s, _ = orc.compress(host, r.eb)
+        return s
+    return orc.decompress(r.stream.cpu().numpy(), r.n, r.F)
 
 
 def snapshot(results):
-    """on_done callback: keep a host copy of each result before its buffer
-    is reused."""
+    """on_done callback: keep a host copy of each result, with the size and
+    status the server recorded, before its buffer is reused."""
     def keep(r):
         if r.op == "compress":
-            results[r.rid] = r.out.cpu().numpy().copy()
+            results[r.rid] = (r.out.cpu().numpy().copy(), r.nbytes, r.status)
         else:
-            results[r.rid] = [o.cpu().numpy().copy() for o in r.out]
+            results[r.rid] = ([o.cpu().numpy().copy() for o in r.out], r.nbytes, r.status)
     return keep
 
 
-def check_same(gpz, reqs, results):
+def check_same(orc, reqs, results):
     for r in reqs:
-        ref = alone(gpz, r)
-        got = results[r.rid]
+        ref = oracle_result(orc, r)
+        got, nbytes, status = results[r.rid]
         if r.op == "compress":
+            assert nbytes == ref.size, f"request {r.rid}: size {nbytes} != oracle {ref.size}"
             assert (got[: ref.size] == ref).all(), f"request {r.rid}: stream differs in the mix"
         else:
+            assert status == 0, f"request {r.rid}: decoder flagged the stream"
             for f in range(r.F):
                 assert (got[f].view(np.uint32) == ref[f].view(np.uint32)).all(), f"request {r.rid}"
 
 
 @pytest.mark.parametrize("mode", ["batched", "per_request"])
-def test_each_result_same_alone_and_in_the_mix(setup, mode):
+def test_each_result_same_alone_and_in_the_mix(setup, orc, mode):
     gpz, serve, reqs = setup
     srv = serve.Server(4 << 30, nstreams=3, max_jobs=16, max_blocks=1 << 14)
     rs = serve.fresh(reqs)
@@ -64,7 +71,7 @@ def test_each_result_same_alone_and_in_the_mix(setup, mode):
     results = {}
     st = srv.run(rs, mode=mode, on_done=snapshot(results))
     torch.cuda.synchronize()
-    check_same(gpz, rs, results)
+    check_same(orc, rs, results)
     assert st["requests"] == len(reqs)
     if mode == "batched":
         assert max(srv.batch_sizes) > 1, "no request was batched with another"

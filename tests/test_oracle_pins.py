@@ -54,6 +54,37 @@ def test_example_stream_by_hand(orc):
     assert tr["count"].tolist() == [3, 3, 6, 3]
 
 
+def golden_fields(g, key="fields"):
+    """Float32 arrays of a golden file; "nan" entries take the file's NaN bits."""
+    out = []
+    for v in g[key]:
+        a = np.array([np.nan if x == "nan" else x for x in v], np.float32)
+        a.view(np.uint32)[np.isnan(a)] = g["nan_bits"]
+        out.append(a)
+    return out
+
+
+def test_four_field_block_by_hand(orc):
+    """Three key axes and an attribute field, with an exactly half-way value
+    (an outlier of a key field) and a NaN (an outlier of an attribute field):
+    every stream word, the permutation and the decoded bits were derived by
+    hand (tests/golden/four_field_block.json)."""
+    g = _gold("four_field_block.json")
+    fields = golden_fields(g)
+    s, perm = orc.compress(fields, g["eb"], B=g["B"], K=g["K"], KF=g["KF"], want_perm=True)
+    assert _words(s).tolist() == g["stream_words"]
+    assert perm.tolist() == g["perm"]
+    out = orc.decompress(s, fields[0].size, len(fields))
+    for got, want in zip(out, golden_fields(g, "decompressed")):
+        assert (got.view(np.uint32) == want.view(np.uint32)).all()
+    tr = orc.block_trace(fields, g["eb"], K=g["K"], KF=g["KF"])
+    assert tr["s"].tolist() == [1, 1, 0]
+    assert tr["outlier"][2].nonzero()[0].tolist() == [7]
+    assert tr["outlier"][3].nonzero()[0].tolist() == [13]
+    assert tr["uniq"].tolist() == [0, 34, 211, 448, 482]
+    assert tr["count"].tolist() == [6, 2, 4, 6, 2]
+
+
 def test_constant_block_by_hand(orc):
     g = _gold("constant_block.json")
     x = np.full(4, 3.0, np.float32)
@@ -413,7 +444,7 @@ def test_bound_check_permutation_and_invalid_entries(orc):
 
 def test_error_stats_closed_form(orc):
     """Every value off by exactly 0.5 over a range of 100: sum of squares
-    n/4, NRMSE 0.005, aggregate PSNR 20 log10(200) dB (Sec. 2 definition)."""
+    n/4, NRMSE 0.005, aggregate PSNR 20 log10(200) dB (Sec. 3.1 definition)."""
     n = 101
     x = [np.arange(n, dtype=np.float32), np.linspace(-50, 50, n).astype(np.float32)]
     y = [a + np.float32(0.5) for a in x]
