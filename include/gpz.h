@@ -128,24 +128,45 @@ int gpz_decompress_async(const void *d_in, uint64_t in_bytes, float *const *h_fi
                          uint64_t n, uint32_t nfields, const gpz_params *p, uint32_t *d_error,
                          void *stream);
 
+/* Device workspace of the reporting calls below (gpz_bound_check,
+ * gpz_error_stats, gpz_stream_stats, gpz_field_range): 32 bytes per field
+ * plus 64, rounded up to 256.  0 for F outside 1..64.  With a workspace these
+ * calls allocate nothing; with d_ws == NULL the library allocates and frees
+ * one per call (GPZ_ENOMEM if it cannot).  A workspace may be reused by
+ * calls that run one after the other on one stream, not by concurrent ones. */
+uint64_t gpz_stats_workspace_bytes(uint32_t nfields);
+
 /* Error-bound verification: recon[f][j] against orig[f][perm[j]] (d_perm
  * NULL: identity).  A pair passes when the float bits are equal or
  * |recon - orig| <= eb in IEEE double.  h_violations[F] receives the failing
  * pair count, h_max_abs_err[F] the largest |recon - orig| over pairs whose
- * difference is a number.  Synchronizes `stream`. */
+ * difference is a number.  A perm entry outside [0, n) counts as a violation
+ * and is not read.  Synchronizes `stream`. */
 int gpz_bound_check(const float *const *h_orig, const float *const *h_recon,
                     const uint32_t *d_perm, uint64_t n, uint32_t nfields, const float *h_eb,
-                    uint64_t *h_violations, double *h_max_abs_err, void *stream);
+                    uint64_t *h_violations, double *h_max_abs_err, void *d_ws, uint64_t ws_bytes,
+                    void *stream);
 
-/* As gpz_bound_check, and also h_sum_sq_err[F] (nullable): the sum over
- * pairs whose difference is a number of (recon - orig)^2 in double, from
- * which the normalized RMSE of every field and the aggregate PSNR of the
- * rate-distortion analysis (Sec. 3.1) follow.  The summation order is not
- * fixed: the sums may differ from a sequential sum in the last bits.
- * Synchronizes `stream`. */
+/* Per-field result of gpz_error_stats. */
+typedef struct {
+    uint64_t violations;  /* pairs outside the bound (as gpz_bound_check) */
+    double max_abs_err;   /* largest |recon - orig| over pairs whose difference is a number */
+    double sum_sq_err;    /* sum of (recon - orig)^2 over those pairs, in double; the
+                             summation order is not fixed (may differ from a sequential
+                             sum in the last bits) */
+    double nrmse;         /* sqrt(sum_sq_err / n) / (max - min); for a zero range 0 when
+                             sum_sq_err is 0, else +inf */
+    float min, max;       /* range of the original field's finite values (0, 0: none) */
+} gpz_field_error;
+
+/* Rate-distortion figures of a reconstruction (Sec. 3.1): the bound check of
+ * every field, its sum of squared errors and normalized RMSE over the
+ * original field's value range (h_out[F]), and the aggregate PSNR
+ * -20 log10 sqrt(mean over fields of NRMSE^2) in dB (*h_psnr, nullable).
+ * Reads orig twice (errors, then its range).  Synchronizes `stream`. */
 int gpz_error_stats(const float *const *h_orig, const float *const *h_recon,
                     const uint32_t *d_perm, uint64_t n, uint32_t nfields, const float *h_eb,
-                    uint64_t *h_violations, double *h_max_abs_err, double *h_sum_sq_err,
+                    gpz_field_error *h_out, double *h_psnr, void *d_ws, uint64_t ws_bytes,
                     void *stream);
 
 /* Structure statistics of a stream of n particles x F fields in device
@@ -155,14 +176,15 @@ int gpz_error_stats(const float *const *h_orig, const float *const *h_recon,
  * on a malformed header or record structure, GPZ_EINVAL when n or F differ
  * from the header.  Synchronizes `stream`. */
 int gpz_stream_stats(const void *d_in, uint64_t in_bytes, uint64_t n, uint32_t nfields,
-                     uint64_t *h_outliers, uint64_t *h_raw_blocks, void *stream);
+                     uint64_t *h_outliers, uint64_t *h_raw_blocks, void *d_ws, uint64_t ws_bytes,
+                     void *stream);
 
 /* Per-field minimum and maximum over finite values (h_minmax[2F]: min, max;
  * 0, 0 for a field with none; a zero extreme is returned as +0.0), used to
  * turn the value-range-relative bounds of the paper's tables into absolute
  * ones.  Synchronizes `stream`. */
 int gpz_field_range(const float *const *h_fields, uint64_t n, uint32_t nfields, float *h_minmax,
-                    void *stream);
+                    void *d_ws, uint64_t ws_bytes, void *stream);
 
 /* Relative bound -> absolute bound of one field: (float)(rel * (hi - lo))
  * computed in double; below 2^-120 (constant field) it is rel itself; above

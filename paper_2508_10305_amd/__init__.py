@@ -23,8 +23,8 @@ GPZ_OK, GPZ_EINVAL, GPZ_ENOSPC, GPZ_ECORRUPT, GPZ_EDEVICE, GPZ_ENOMEM, GPZ_EUNSU
 EXPORTS = (
     "gpz_default_params", "gpz_max_compressed_bytes", "gpz_compress_workspace_bytes",
     "gpz_decompress_workspace_bytes", "gpz_compress", "gpz_compress_async", "gpz_decompress",
-    "gpz_decompress_async", "gpz_bound_check", "gpz_error_stats", "gpz_stream_stats",
-    "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
+    "gpz_decompress_async", "gpz_stats_workspace_bytes", "gpz_bound_check", "gpz_error_stats",
+    "gpz_stream_stats", "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
     "gpz_set_timing", "gpz_set_timing_kinds", "gpz_timing_collect", "gpz_strerror",
     "gpz_default_batch_config",
     "gpz_batch_workspace_bytes", "gpz_batch_create", "gpz_batch_rebind", "gpz_batch_compress",
@@ -59,6 +59,12 @@ class BatchConfig(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_uint32), ("tile", ctypes.c_uint32),
                 ("use_graph", ctypes.c_uint32), ("max_jobs", ctypes.c_uint32),
                 ("max_blocks", ctypes.c_uint64)]
+
+
+class FieldError(ctypes.Structure):
+    _fields_ = [("violations", ctypes.c_uint64), ("max_abs_err", ctypes.c_double),
+                ("sum_sq_err", ctypes.c_double), ("nrmse", ctypes.c_double),
+                ("min", ctypes.c_float), ("max", ctypes.c_float)]
 
 
 class Info(ctypes.Structure):
@@ -96,13 +102,16 @@ def _lib():
         L.gpz_decompress.restype = ctypes.c_int
         L.gpz_decompress_async.argtypes = [vp, u64, vp, u64, u32, pp, vp, vp]
         L.gpz_decompress_async.restype = ctypes.c_int
-        L.gpz_bound_check.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp, vp]
+        L.gpz_stats_workspace_bytes.argtypes = [u32]
+        L.gpz_stats_workspace_bytes.restype = u64
+        L.gpz_bound_check.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp, vp, u64, vp]
         L.gpz_bound_check.restype = ctypes.c_int
-        L.gpz_error_stats.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp, vp, vp]
+        L.gpz_error_stats.argtypes = [vp, vp, vp, u64, u32, vp, ctypes.POINTER(FieldError),
+                                      ctypes.POINTER(ctypes.c_double), vp, u64, vp]
         L.gpz_error_stats.restype = ctypes.c_int
-        L.gpz_stream_stats.argtypes = [vp, u64, u64, u32, vp, vp, vp]
+        L.gpz_stream_stats.argtypes = [vp, u64, u64, u32, vp, vp, vp, u64, vp]
         L.gpz_stream_stats.restype = ctypes.c_int
-        L.gpz_field_range.argtypes = [vp, u64, u32, vp, vp]
+        L.gpz_field_range.argtypes = [vp, u64, u32, vp, vp, u64, vp]
         L.gpz_field_range.restype = ctypes.c_int
         L.gpz_rel_to_abs.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
         L.gpz_rel_to_abs.restype = ctypes.c_float
@@ -291,8 +300,22 @@ def decompress_async(stream_bytes, n: int, nfields: int, out: List, err, p: Opti
     _check(rc, "gpz_decompress_async")
 
 
-def bound_check(orig: Sequence, recon: Sequence, eb, perm=None, stream=None
+def stats_workspace(nfields: int, device="cuda"):
+    """A device workspace for the reporting calls (bound check, error and
+    stream statistics, field range) of up to `nfields` fields."""
+    torch = _torch()
+    return torch.empty(int(_lib().gpz_stats_workspace_bytes(nfields)), dtype=torch.uint8,
+                       device=device)
+
+
+def _ws_args(ws):
+    return (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
+
+
+def bound_check(orig: Sequence, recon: Sequence, eb, perm=None, stream=None, ws=None
                 ) -> Tuple[np.ndarray, np.ndarray]:
+    """(violations, max abs error) per field; `ws` from stats_workspace (None:
+    the library allocates one for the call)."""
     F = len(orig)
     n = _check_fields(orig)
     _check_fields(recon, n)
@@ -304,57 +327,57 @@ def bound_check(orig: Sequence, recon: Sequence, eb, perm=None, stream=None
                                 perm.data_ptr() if perm is not None else None, n, F,
                                 ebs.ctypes.data_as(ctypes.c_void_p),
                                 viol.ctypes.data_as(ctypes.c_void_p),
-                                mx.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+                                mx.ctypes.data_as(ctypes.c_void_p), *_ws_args(ws),
+                                _stream_handle(stream))
     _check(rc, "gpz_bound_check")
     return viol, mx
 
 
-def error_stats(orig: Sequence, recon: Sequence, eb, perm=None, stream=None) -> dict:
-    """Bound check plus rate-distortion figures (Sec. 3.1): per-field violation
-    counts, maximum and summed squared errors, normalized RMSE over each
-    original field's range, and the aggregate PSNR in dB."""
+def error_stats(orig: Sequence, recon: Sequence, eb, perm=None, stream=None, ws=None) -> dict:
+    """Bound check plus the rate-distortion figures of Sec. 3.1, all computed
+    by the library: per-field violation counts, maximum and summed squared
+    errors, normalized RMSE over each original field's range, and the
+    aggregate PSNR in dB."""
     F = len(orig)
     n = _check_fields(orig)
     _check_fields(recon, n)
     ebs = _eb_array(eb, F)
-    viol = np.zeros(F, np.uint64)
-    mx = np.zeros(F, np.float64)
-    ss = np.zeros(F, np.float64)
+    res = (FieldError * F)()
+    psnr = ctypes.c_double(0.0)
     rc = _lib().gpz_error_stats(ctypes.cast(_ptr_array(orig), ctypes.c_void_p),
                                 ctypes.cast(_ptr_array(recon), ctypes.c_void_p),
                                 perm.data_ptr() if perm is not None else None, n, F,
-                                ebs.ctypes.data_as(ctypes.c_void_p),
-                                viol.ctypes.data_as(ctypes.c_void_p),
-                                mx.ctypes.data_as(ctypes.c_void_p),
-                                ss.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+                                ebs.ctypes.data_as(ctypes.c_void_p), res, ctypes.byref(psnr),
+                                *_ws_args(ws), _stream_handle(stream))
     _check(rc, "gpz_error_stats")
-    mm = field_range(orig, stream)
-    rng = mm[:, 1].astype(np.float64) - mm[:, 0].astype(np.float64)
-    rmse = np.sqrt(ss / n) if n else np.zeros(F)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        nrmse = np.where(rng > 0, rmse / np.where(rng > 0, rng, 1.0),
-                         np.where(rmse == 0, 0.0, np.inf))
-        psnr = float(-20.0 * np.log10(np.sqrt(np.mean(nrmse ** 2))))
-    return {"violations": viol, "max_abs_err": mx, "sum_sq": ss, "nrmse": nrmse, "psnr": psnr}
+    return {"violations": np.array([r.violations for r in res], np.uint64),
+            "max_abs_err": np.array([r.max_abs_err for r in res], np.float64),
+            "sum_sq": np.array([r.sum_sq_err for r in res], np.float64),
+            "nrmse": np.array([r.nrmse for r in res], np.float64),
+            "range": np.array([[r.min, r.max] for r in res], np.float32),
+            "psnr": psnr.value}
 
 
-def stream_stats(stream_bytes, n: int, nfields: int, stream=None):
+def stream_stats(stream_bytes, n: int, nfields: int, stream=None, ws=None):
     """(outliers per field, raw blocks) of a stream held in a uint8 CUDA tensor."""
     out = np.zeros(nfields, np.uint64)
     raw = np.zeros(1, np.uint64)
     rc = _lib().gpz_stream_stats(stream_bytes.data_ptr(), stream_bytes.numel(), n, nfields,
                                  out.ctypes.data_as(ctypes.c_void_p),
-                                 raw.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+                                 raw.ctypes.data_as(ctypes.c_void_p), *_ws_args(ws),
+                                 _stream_handle(stream))
     _check(rc, "gpz_stream_stats")
     return out, int(raw[0])
 
 
-def field_range(fields: Sequence, stream=None) -> np.ndarray:
+def field_range(fields: Sequence, stream=None, ws=None) -> np.ndarray:
+    """(F, 2) float32 array of each field's finite minimum and maximum."""
     F = len(fields)
     n = _check_fields(fields)
     mm = np.zeros(2 * F, np.float32)
     rc = _lib().gpz_field_range(ctypes.cast(_ptr_array(fields), ctypes.c_void_p), n, F,
-                                mm.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+                                mm.ctypes.data_as(ctypes.c_void_p), *_ws_args(ws),
+                                _stream_handle(stream))
     _check(rc, "gpz_field_range")
     return mm.reshape(F, 2)
 
@@ -363,9 +386,10 @@ def rel_to_abs(rel: float, lo: float, hi: float) -> float:
     return float(np.float32(_lib().gpz_rel_to_abs(rel, lo, hi)))
 
 
-def rel_ebs(fields: Sequence, rel: float, stream=None) -> np.ndarray:
-    """Absolute per-field bounds for a value-range-relative bound."""
-    mm = field_range(fields, stream)
+def rel_ebs(fields: Sequence, rel: float, stream=None, ws=None) -> np.ndarray:
+    """Absolute per-field bounds for a value-range-relative bound (the field
+    range kernel, then gpz_rel_to_abs per field)."""
+    mm = field_range(fields, stream, ws)
     return np.array([rel_to_abs(rel, float(a), float(b)) for a, b in mm], np.float32)
 
 

@@ -20,12 +20,23 @@ HIPCC_FLAGS = [
 ]
 
 
+BENCH_LIB = os.path.join(OUT_DIR, "libgpzbench.so")
+BENCH_SOURCES = ["membench.hip"]
+
+
 def build_lib(verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 and link libgpz.so (always rebuilds)."""
+    """Compile every HIP source for gfx950 and link libgpz.so and the
+    bandwidth probes' libgpzbench.so (always rebuilds)."""
+    _link(SOURCES, LIB, verbose)
+    _link(BENCH_SOURCES, BENCH_LIB, verbose)
+    return LIB
+
+
+def _link(sources, lib, verbose):
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
-    for src in SOURCES:
+    for src in sources:
         obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
         cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
@@ -35,15 +46,15 @@ def build_lib(verbose: bool = False) -> str:
         if verbose and r.stderr:
             print(r.stderr)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":

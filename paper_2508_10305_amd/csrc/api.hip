@@ -105,6 +105,7 @@ CompressWs layout(uint64_t n, uint32_t F, uint32_t B, char* base) {
 }
 
 int to_status(hipError_t e) { return e == hipSuccess ? GPZ_OK : GPZ_EDEVICE; }
+bool alloc_fault();
 
 // Shared body of gpz_compress / gpz_compress_async.
 int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const float* h_eb,
@@ -130,8 +131,7 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     bool owned = false;
     if (!ws) {
         if (!sync) return GPZ_EINVAL;
-        if (getenv("GPZ_FAULT") && strcmp(getenv("GPZ_FAULT"), "alloc") == 0) return GPZ_ENOMEM;
-        if (hipMalloc(&ws, probe.bytes) != hipSuccess) return GPZ_ENOMEM;
+        if (alloc_fault() || hipMalloc(&ws, probe.bytes) != hipSuccess) return GPZ_ENOMEM;
         owned = true;
     } else if (ws_bytes < probe.bytes) {
         return GPZ_EINVAL;
@@ -220,6 +220,71 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
         (void)hipFree(ws);
     }
     return rc;
+}
+
+// Workspace of the reporting calls (error statistics, bound check, stream
+// statistics, field range): 32 bytes per field and a few flags.
+uint64_t stats_ws_bytes(uint32_t F) { return align256(32ull * F + 64); }
+
+// The library's own allocations; GPZ_FAULT=alloc makes them fail (tests of
+// the allocation-free paths).
+bool alloc_fault() {
+    const char* e = getenv("GPZ_FAULT");
+    return e && strcmp(e, "alloc") == 0;
+}
+
+// The caller's workspace (at least `need` bytes), or with d_ws NULL one the
+// library allocates for the call (*owned, freed by the caller of take_ws).
+int take_ws(void* d_ws, uint64_t ws_bytes, uint64_t need, char** out, bool* owned) {
+    *owned = false;
+    if (d_ws) {
+        if (ws_bytes < need) return GPZ_EINVAL;
+        *out = static_cast<char*>(d_ws);
+        return GPZ_OK;
+    }
+    if (alloc_fault() || hipMalloc(reinterpret_cast<void**>(out), need) != hipSuccess)
+        return GPZ_ENOMEM;
+    *owned = true;
+    return GPZ_OK;
+}
+
+// Minimum / maximum keys (order-preserving integers of the float bits) set to
+// the identities of atomicMin / atomicMax, by a kernel (graph-capturable).
+int range_keys_reset(int* keys, uint32_t F, hipStream_t s) {
+    int rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(keys), 0x7FFFFFFFu, F, s));
+    if (rc == GPZ_OK)
+        rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(keys) + F, 0x80000000u, F, s));
+    return rc;
+}
+
+// Field range from its keys: 0, 0 when no finite value was seen, a zero
+// extreme as +0.0.
+void range_from_keys(int mn, int mx, float* lo, float* hi) {
+    *lo = 0.0f;
+    *hi = 0.0f;
+    if (mn <= mx) {  // some finite value was seen
+        const int a = mn ^ ((mn >> 31) & 0x7FFFFFFF), b = mx ^ ((mx >> 31) & 0x7FFFFFFF);
+        memcpy(lo, &a, 4);
+        memcpy(hi, &b, 4);
+        if (*lo == 0.0f) *lo = 0.0f;
+        if (*hi == 0.0f) *hi = 0.0f;
+    }
+}
+
+// Field range of F device arrays through 8F bytes of device scratch `keys`;
+// writes h_minmax[2F] and synchronizes the stream.
+int field_range_into(const float* const* h_fields, uint64_t n, uint32_t F, int* keys,
+                     float* h_minmax, hipStream_t s) {
+    int rc = range_keys_reset(keys, F, s);
+    if (rc == GPZ_OK && n > 0) rc = to_status(launch_field_range(h_fields, n, F, keys, s));
+    int h[2 * kMaxFields];
+    if (rc == GPZ_OK)
+        rc = to_status(hipMemcpyAsync(h, keys, 8ull * F, hipMemcpyDeviceToHost, s));
+    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    else (void)hipStreamSynchronize(s);  // queued kernels may still use the keys
+    if (rc) return rc;
+    for (uint32_t f = 0; f < F; f++) range_from_keys(h[f], h[F + f], &h_minmax[2 * f], &h_minmax[2 * f + 1]);
+    return GPZ_OK;
 }
 
 }  // namespace
@@ -319,7 +384,7 @@ int gpz_decompress(const void* d_in, uint64_t in_bytes, float* const* h_fields_o
     uint32_t* err = static_cast<uint32_t*>(d_ws);
     bool owned = false;
     if (!err) {
-        if (hipMalloc(&err, 256) != hipSuccess) return GPZ_ENOMEM;
+        if (alloc_fault() || hipMalloc(&err, 256) != hipSuccess) return GPZ_ENOMEM;
         owned = true;
     } else if (ws_bytes < gpz_decompress_workspace_bytes()) {
         return GPZ_EINVAL;
@@ -348,9 +413,66 @@ int gpz_decompress_async(const void* d_in, uint64_t in_bytes, float* const* h_fi
                            static_cast<hipStream_t>(stream), false);
 }
 
+uint64_t gpz_stats_workspace_bytes(uint32_t nfields) {
+    if (nfields < 1 || nfields > kMaxFields) return 0;
+    return stats_ws_bytes(nfields);
+}
+
 int gpz_error_stats(const float* const* h_orig, const float* const* h_recon,
                     const uint32_t* d_perm, uint64_t n, uint32_t nfields, const float* h_eb,
-                    uint64_t* h_violations, double* h_max_abs_err, double* h_sum_sq_err,
+                    gpz_field_error* h_out, double* h_psnr, void* d_ws, uint64_t ws_bytes,
+                    void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nfields < 1 || nfields > kMaxFields || !h_eb || !h_out) return GPZ_EINVAL;
+    if (n > 0 && (!h_orig || !h_recon)) return GPZ_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < nfields; f++)
+        if (!h_orig[f] || !h_recon[f]) return GPZ_EINVAL;
+    const uint32_t F = nfields;
+    char* ws = nullptr;
+    bool owned = false;
+    int rc = take_ws(d_ws, ws_bytes, stats_ws_bytes(F), &ws, &owned);
+    if (rc) return rc;
+    // per field: violation count, maximum-error bits, sum of squares (8 bytes
+    // each), then the range keys of the originals (2 x 4 bytes)
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws);
+    int* keys = reinterpret_cast<int*>(acc + 3 * F);
+    double* sumsq = reinterpret_cast<double*>(acc + 2 * F);
+    rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, 6ull * F, s));
+    if (rc == GPZ_OK) rc = range_keys_reset(keys, F, s);
+    if (rc == GPZ_OK && n > 0)
+        rc = to_status(launch_bound_check(h_orig, h_recon, d_perm, n, F, h_eb, acc, acc + F,
+                                          sumsq, s));
+    if (rc == GPZ_OK && n > 0) rc = to_status(launch_field_range(h_orig, n, F, keys, s));
+    std::vector<unsigned long long> h(4 * F);
+    if (rc == GPZ_OK)
+        rc = to_status(hipMemcpyAsync(h.data(), acc, 32ull * F, hipMemcpyDeviceToHost, s));
+    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    else (void)hipStreamSynchronize(s);  // queued kernels may still use the buffer
+    if (owned) (void)hipFree(ws);
+    if (rc) return rc;
+    // Normalized RMSE of every field over its original finite range, and the
+    // aggregate PSNR of the rate-distortion analysis (Sec. 3.1):
+    // -20 log10 sqrt(mean over fields of NRMSE^2).
+    const int* hk = reinterpret_cast<const int*>(h.data() + 3 * F);
+    double mean = 0.0;
+    for (uint32_t f = 0; f < F; f++) {
+        gpz_field_error& e = h_out[f];
+        e.violations = h[f];
+        memcpy(&e.max_abs_err, &h[F + f], 8);
+        memcpy(&e.sum_sq_err, &h[2 * F + f], 8);
+        range_from_keys(hk[f], hk[F + f], &e.min, &e.max);
+        const double range = (double)e.max - (double)e.min;
+        const double rmse = n ? sqrt(e.sum_sq_err / (double)n) : 0.0;
+        e.nrmse = range > 0.0 ? rmse / range : (rmse == 0.0 ? 0.0 : INFINITY);
+        mean += e.nrmse * e.nrmse;
+    }
+    if (h_psnr) *h_psnr = -20.0 * log10(sqrt(mean / (double)F));
+    return GPZ_OK;
+}
+
+int gpz_bound_check(const float* const* h_orig, const float* const* h_recon,
+                    const uint32_t* d_perm, uint64_t n, uint32_t nfields, const float* h_eb,
+                    uint64_t* h_violations, double* h_max_abs_err, void* d_ws, uint64_t ws_bytes,
                     void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (nfields < 1 || nfields > kMaxFields || !h_eb || !h_violations || !h_max_abs_err)
@@ -358,46 +480,37 @@ int gpz_error_stats(const float* const* h_orig, const float* const* h_recon,
     if (n > 0 && (!h_orig || !h_recon)) return GPZ_EINVAL;
     for (uint32_t f = 0; n > 0 && f < nfields; f++)
         if (!h_orig[f] || !h_recon[f]) return GPZ_EINVAL;
-    // counts, maximum-error bits and sums of squares: 3 x 8 bytes per field
-    unsigned long long* acc = nullptr;
-    if (hipMalloc(&acc, 24ull * nfields) != hipSuccess) return GPZ_ENOMEM;
-    double* sumsq = h_sum_sq_err ? reinterpret_cast<double*>(acc + 2 * nfields) : nullptr;
-    int rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, 6ull * nfields, s));
-    if (rc == GPZ_OK && n > 0)
-        rc = to_status(launch_bound_check(h_orig, h_recon, d_perm, n, nfields, h_eb, acc,
-                                          acc + nfields, sumsq, s));
-    std::vector<unsigned long long> h(3 * nfields);
-    if (rc == GPZ_OK)
-        rc = to_status(hipMemcpyAsync(h.data(), acc, 24ull * nfields, hipMemcpyDeviceToHost, s));
-    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
-    else (void)hipStreamSynchronize(s);  // queued kernels may still use the buffer
-    (void)hipFree(acc);
+    const uint32_t F = nfields;
+    char* ws = nullptr;
+    bool owned = false;
+    int rc = take_ws(d_ws, ws_bytes, stats_ws_bytes(F), &ws, &owned);
     if (rc) return rc;
-    for (uint32_t f = 0; f < nfields; f++) {
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws);
+    rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, 4ull * F, s));
+    if (rc == GPZ_OK && n > 0)
+        rc = to_status(launch_bound_check(h_orig, h_recon, d_perm, n, F, h_eb, acc, acc + F,
+                                          nullptr, s));
+    std::vector<unsigned long long> h(2 * F);
+    if (rc == GPZ_OK)
+        rc = to_status(hipMemcpyAsync(h.data(), acc, 16ull * F, hipMemcpyDeviceToHost, s));
+    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
+    else (void)hipStreamSynchronize(s);
+    if (owned) (void)hipFree(ws);
+    if (rc) return rc;
+    for (uint32_t f = 0; f < F; f++) {
         h_violations[f] = h[f];
-        double d;
-        memcpy(&d, &h[nfields + f], 8);
-        h_max_abs_err[f] = d;
-        if (h_sum_sq_err) {
-            memcpy(&d, &h[2 * nfields + f], 8);
-            h_sum_sq_err[f] = d;
-        }
+        memcpy(&h_max_abs_err[f], &h[F + f], 8);
     }
     return GPZ_OK;
 }
 
-int gpz_bound_check(const float* const* h_orig, const float* const* h_recon,
-                    const uint32_t* d_perm, uint64_t n, uint32_t nfields, const float* h_eb,
-                    uint64_t* h_violations, double* h_max_abs_err, void* stream) {
-    return gpz_error_stats(h_orig, h_recon, d_perm, n, nfields, h_eb, h_violations,
-                           h_max_abs_err, nullptr, stream);
-}
-
 int gpz_stream_stats(const void* d_in, uint64_t in_bytes, uint64_t n, uint32_t nfields,
-                     uint64_t* h_outliers, uint64_t* h_raw_blocks, void* stream) {
+                     uint64_t* h_outliers, uint64_t* h_raw_blocks, void* d_ws, uint64_t ws_bytes,
+                     void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!d_in || nfields < 1 || nfields > kMaxFields || !h_outliers || !h_raw_blocks)
         return GPZ_EINVAL;
+    if (d_ws && ws_bytes < stats_ws_bytes(nfields)) return GPZ_EINVAL;
     if (in_bytes < 4 * kHeaderWords) return GPZ_ECORRUPT;
     uint32_t hdr[kHeaderWords];
     if (hipMemcpyAsync(hdr, d_in, sizeof(hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -409,9 +522,12 @@ int gpz_stream_stats(const void* d_in, uint64_t in_bytes, uint64_t n, uint32_t n
     if (info.n != n || info.nfields != nfields) return GPZ_EINVAL;
     const uint64_t prefix = prefix_words(n, nfields, info.block_size);
     if (4 * prefix > in_bytes) return GPZ_ECORRUPT;
+    char* ws = nullptr;
+    bool owned = false;
+    rc = take_ws(d_ws, ws_bytes, stats_ws_bytes(nfields), &ws, &owned);
+    if (rc) return rc;
     // outliers per field, raw blocks, error flag
-    unsigned long long* acc = nullptr;
-    if (hipMalloc(&acc, 8ull * (nfields + 2)) != hipSuccess) return GPZ_ENOMEM;
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(ws);
     uint32_t* err = reinterpret_cast<uint32_t*>(acc + nfields + 1);
     rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 0u, 2ull * (nfields + 2), s));
     if (rc == GPZ_OK)
@@ -422,7 +538,7 @@ int gpz_stream_stats(const void* d_in, uint64_t in_bytes, uint64_t n, uint32_t n
         rc = to_status(hipMemcpyAsync(h.data(), acc, 8ull * (nfields + 2), hipMemcpyDeviceToHost, s));
     if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
     else (void)hipStreamSynchronize(s);  // queued kernels may still use the buffer
-    (void)hipFree(acc);
+    if (owned) (void)hipFree(ws);
     if (rc) return rc;
     if (h[nfields + 1] & 0xFFFFFFFFull) return GPZ_ECORRUPT;
     for (uint32_t f = 0; f < nfields; f++) h_outliers[f] = h[f];
@@ -431,40 +547,19 @@ int gpz_stream_stats(const void* d_in, uint64_t in_bytes, uint64_t n, uint32_t n
 }
 
 int gpz_field_range(const float* const* h_fields, uint64_t n, uint32_t nfields, float* h_minmax,
-                    void* stream) {
+                    void* d_ws, uint64_t ws_bytes, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (nfields < 1 || nfields > kMaxFields || !h_minmax) return GPZ_EINVAL;
     if (n > 0 && !h_fields) return GPZ_EINVAL;
     for (uint32_t f = 0; n > 0 && f < nfields; f++)
         if (!h_fields[f]) return GPZ_EINVAL;
-    int* keys = nullptr;
-    if (hipMalloc(&keys, 8ull * nfields) != hipSuccess) return GPZ_ENOMEM;
-    int rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(keys), 0x7FFFFFFFu, nfields, s));
-    if (rc == GPZ_OK)
-        rc = to_status(launch_fill_u32(reinterpret_cast<uint32_t*>(keys) + nfields, 0x80000000u,
-                                       nfields, s));
-    if (rc == GPZ_OK && n > 0) rc = to_status(launch_field_range(h_fields, n, nfields, keys, s));
-    std::vector<int> h(2 * nfields);
-    if (rc == GPZ_OK)
-        rc = to_status(hipMemcpyAsync(h.data(), keys, 8ull * nfields, hipMemcpyDeviceToHost, s));
-    if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
-    else (void)hipStreamSynchronize(s);  // queued kernels may still use the buffer
-    (void)hipFree(keys);
+    char* ws = nullptr;
+    bool owned = false;
+    int rc = take_ws(d_ws, ws_bytes, stats_ws_bytes(nfields), &ws, &owned);
     if (rc) return rc;
-    for (uint32_t f = 0; f < nfields; f++) {
-        int mn = h[f], mx = h[nfields + f];
-        float lo = 0.0f, hi = 0.0f;
-        if (mn <= mx) {  // some finite value was seen
-            int a = mn ^ ((mn >> 31) & 0x7FFFFFFF), b = mx ^ ((mx >> 31) & 0x7FFFFFFF);
-            memcpy(&lo, &a, 4);
-            memcpy(&hi, &b, 4);
-            if (lo == 0.0f) lo = 0.0f;
-            if (hi == 0.0f) hi = 0.0f;
-        }
-        h_minmax[2 * f] = lo;
-        h_minmax[2 * f + 1] = hi;
-    }
-    return GPZ_OK;
+    rc = field_range_into(h_fields, n, nfields, reinterpret_cast<int*>(ws), h_minmax, s);
+    if (owned) (void)hipFree(ws);
+    return rc;
 }
 
 float gpz_rel_to_abs(float rel, float lo, float hi) {

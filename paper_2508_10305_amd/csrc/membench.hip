@@ -1,0 +1,137 @@
+// Achievable-bandwidth probes for the roofline reference: a streaming read
+// (every byte loaded once, folded into a value that is never stored unless
+// it equals a sentinel) and a streaming copy, each with a choice of launch
+// geometry, loads in flight per lane and cache policy.  The benchmark sweeps
+// these shapes and reports the best rate as the HBM rate a kernel of this
+// library can reach on the GPU at hand.  Not part of the compressor.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gpz_bench.h"
+
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ u32x4 load16(const u32x4* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void store16(u32x4* p, u32x4 v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Workgroup g owns chunks of U * 256 consecutive 16-byte vectors, g, g +
+// gridDim.x, ...: each load instruction of a wave covers 1 KB, the U loads
+// of a lane are issued before any is used.
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void read_chunks(const u32x4* __restrict__ x, uint64_t nv,
+                                                   uint32_t* __restrict__ sink) {
+    uint32_t acc = 0;
+    const uint64_t chunk = (uint64_t)U * 256;
+    for (uint64_t c = (uint64_t)blockIdx.x * chunk; c < nv; c += (uint64_t)gridDim.x * chunk) {
+        u32x4 v[U];
+        if (c + chunk <= nv) {
+#pragma unroll
+            for (int k = 0; k < U; k++) v[k] = load16<NT>(x + c + 256 * k + threadIdx.x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                const uint64_t i = c + 256 * k + threadIdx.x;
+                v[k] = i < nv ? load16<NT>(x + i) : u32x4{0, 0, 0, 0};
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < U; k++) acc ^= v[k].x ^ v[k].y ^ v[k].z ^ v[k].w;
+    }
+    if (acc == 0x9E3779B9u) sink[0] = acc;  // keeps the loads; practically never taken
+}
+
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void copy_chunks(const u32x4* __restrict__ x,
+                                                   u32x4* __restrict__ y, uint64_t nv) {
+    const uint64_t chunk = (uint64_t)U * 256;
+    for (uint64_t c = (uint64_t)blockIdx.x * chunk; c < nv; c += (uint64_t)gridDim.x * chunk) {
+        u32x4 v[U];
+        if (c + chunk <= nv) {
+#pragma unroll
+            for (int k = 0; k < U; k++) v[k] = load16<NT>(x + c + 256 * k + threadIdx.x);
+#pragma unroll
+            for (int k = 0; k < U; k++) store16<NT>(y + c + 256 * k + threadIdx.x, v[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                const uint64_t i = c + 256 * k + threadIdx.x;
+                if (i < nv) store16<NT>(y + i, load16<NT>(x + i));
+            }
+        }
+    }
+}
+
+template <int U>
+hipError_t launch_read_u(const void* x, uint64_t nv, uint32_t grid, uint32_t nt, uint32_t* sink,
+                         hipStream_t s) {
+    if (nt) hipLaunchKernelGGL((read_chunks<U, true>), dim3(grid), dim3(256), 0, s,
+                               static_cast<const u32x4*>(x), nv, sink);
+    else hipLaunchKernelGGL((read_chunks<U, false>), dim3(grid), dim3(256), 0, s,
+                            static_cast<const u32x4*>(x), nv, sink);
+    return hipGetLastError();
+}
+
+template <int U>
+hipError_t launch_copy_u(const void* x, void* y, uint64_t nv, uint32_t grid, uint32_t nt,
+                         hipStream_t s) {
+    if (nt) hipLaunchKernelGGL((copy_chunks<U, true>), dim3(grid), dim3(256), 0, s,
+                               static_cast<const u32x4*>(x), static_cast<u32x4*>(y), nv);
+    else hipLaunchKernelGGL((copy_chunks<U, false>), dim3(grid), dim3(256), 0, s,
+                            static_cast<const u32x4*>(x), static_cast<u32x4*>(y), nv);
+    return hipGetLastError();
+}
+
+bool shape_ok(const void* p, uint64_t bytes, uint32_t grid) {
+    return p && bytes % 16 == 0 && (reinterpret_cast<uintptr_t>(p) & 15u) == 0 && grid >= 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gpzb_read(const void* d_x, uint64_t bytes, uint32_t grid, uint32_t unroll, uint32_t nt,
+              uint32_t* d_sink, void* stream) {
+    if (!shape_ok(d_x, bytes, grid) || !d_sink) return -1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t nv = bytes / 16;
+    hipError_t e;
+    switch (unroll) {
+        case 1: e = launch_read_u<1>(d_x, nv, grid, nt, d_sink, s); break;
+        case 2: e = launch_read_u<2>(d_x, nv, grid, nt, d_sink, s); break;
+        case 4: e = launch_read_u<4>(d_x, nv, grid, nt, d_sink, s); break;
+        case 8: e = launch_read_u<8>(d_x, nv, grid, nt, d_sink, s); break;
+        case 16: e = launch_read_u<16>(d_x, nv, grid, nt, d_sink, s); break;
+        default: return -1;
+    }
+    return e == hipSuccess ? 0 : -4;
+}
+
+int gpzb_copy(const void* d_x, void* d_y, uint64_t bytes, uint32_t grid, uint32_t unroll,
+              uint32_t nt, void* stream) {
+    if (!shape_ok(d_x, bytes, grid) || !shape_ok(d_y, bytes, grid)) return -1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t nv = bytes / 16;
+    hipError_t e;
+    switch (unroll) {
+        case 1: e = launch_copy_u<1>(d_x, d_y, nv, grid, nt, s); break;
+        case 2: e = launch_copy_u<2>(d_x, d_y, nv, grid, nt, s); break;
+        case 4: e = launch_copy_u<4>(d_x, d_y, nv, grid, nt, s); break;
+        case 8: e = launch_copy_u<8>(d_x, d_y, nv, grid, nt, s); break;
+        case 16: e = launch_copy_u<16>(d_x, d_y, nv, grid, nt, s); break;
+        default: return -1;
+    }
+    return e == hipSuccess ? 0 : -4;
+}
+
+}  // extern "C"

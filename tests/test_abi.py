@@ -121,9 +121,29 @@ def test_batch_and_stats_entry_points_reject_bad_arguments(gpz):
     assert L.gpz_batch_create(ctypes.byref(b), jobs, 1, ctypes.byref(p), None, None, 0) == \
         gpz.GPZ_EINVAL
     assert L.gpz_batch_create(None, jobs, 1, None, None, None, 0) == gpz.GPZ_EINVAL
-    assert L.gpz_error_stats(None, None, None, 10, 0, None, None, None, None, None) == \
+    assert L.gpz_error_stats(None, None, None, 10, 0, None, None, None, None, 0, None) == \
         gpz.GPZ_EINVAL
-    assert L.gpz_stream_stats(None, 100, 10, 3, None, None, None) == gpz.GPZ_EINVAL
+    assert L.gpz_stream_stats(None, 100, 10, 3, None, None, None, 0, None) == gpz.GPZ_EINVAL
+    assert L.gpz_stats_workspace_bytes(0) == 0 and L.gpz_stats_workspace_bytes(65) == 0
+    assert L.gpz_stats_workspace_bytes(64) >= 32 * 64
+    # a workspace smaller than gpz_stats_workspace_bytes is refused before any device work
+    small = L.gpz_stats_workspace_bytes(3) - 1
+    fake = (ctypes.c_void_p * 3)(0x1000, 0x2000, 0x3000)  # never dereferenced on the host
+    ebs = np.full(3, 1e-3, np.float32)
+    mm = np.zeros(6, np.float32)
+    assert L.gpz_field_range(ctypes.cast(fake, ctypes.c_void_p), 10, 3,
+                             mm.ctypes.data_as(ctypes.c_void_p), 0x5000, small, None) == \
+        gpz.GPZ_EINVAL
+    res = (gpz.FieldError * 3)()
+    assert L.gpz_error_stats(ctypes.cast(fake, ctypes.c_void_p), ctypes.cast(fake, ctypes.c_void_p),
+                             None, 10, 3, ebs.ctypes.data_as(ctypes.c_void_p), res, None, 0x5000,
+                             small, None) == gpz.GPZ_EINVAL
+    v = np.zeros(3, np.uint64)
+    m = np.zeros(3, np.float64)
+    assert L.gpz_bound_check(ctypes.cast(fake, ctypes.c_void_p), ctypes.cast(fake, ctypes.c_void_p),
+                             None, 10, 3, ebs.ctypes.data_as(ctypes.c_void_p),
+                             v.ctypes.data_as(ctypes.c_void_p), m.ctypes.data_as(ctypes.c_void_p),
+                             0x5000, small, None) == gpz.GPZ_EINVAL
     ms = (ctypes.c_double * 5)()
     cnt = (ctypes.c_uint32 * 5)()
     assert L.gpz_timing_collect(None, cnt, 5) == gpz.GPZ_EINVAL
@@ -158,3 +178,11 @@ def test_injected_allocation_failure(gpz, monkeypatch):
                         ebs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), 0x4000, 1 << 20,
                         ctypes.byref(nbytes), None, None, 0, None)
     assert rc == gpz.GPZ_ENOMEM
+    # the reporting calls allocate only when no workspace is given
+    mm = np.zeros(6, np.float32)
+    assert L.gpz_field_range(ctypes.cast(fake, ctypes.c_void_p), 5000, 3,
+                             mm.ctypes.data_as(ctypes.c_void_p), None, 0, None) == gpz.GPZ_ENOMEM
+    res = (gpz.FieldError * 3)()
+    assert L.gpz_error_stats(ctypes.cast(fake, ctypes.c_void_p), ctypes.cast(fake, ctypes.c_void_p),
+                             None, 5000, 3, ebs.ctypes.data_as(ctypes.c_void_p), res, None, None,
+                             0, None) == gpz.GPZ_ENOMEM

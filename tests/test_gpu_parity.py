@@ -443,7 +443,42 @@ def test_error_stats_parity(gpz, orc):
     rv, rm = orc.bound_check(host, ref_out, eb, perm=perm.cpu().numpy().astype(np.uint32))
     assert (st["violations"] == rv).all() and (st["max_abs_err"] == rm).all()
     assert np.allclose(st["sum_sq"], ref["sum_sq"], rtol=1e-9, atol=0)
+    assert np.allclose(st["nrmse"], ref["nrmse"], rtol=1e-9, atol=0)
     assert abs(st["psnr"] - ref["psnr"]) <= 1e-9 * abs(ref["psnr"])
+    assert (st["range"].view(np.uint32) == orc.field_range(host).view(np.uint32)).all()
+
+
+def test_reporting_calls_allocate_nothing_with_a_workspace(gpz, orc, monkeypatch):
+    """With a caller workspace the field range, error statistics, bound check
+    and stream statistics make no allocation: they succeed while every
+    library allocation is made to fail (GPZ_FAULT=alloc), and give the
+    oracle's results; without one they report GPZ_ENOMEM."""
+    from paper_2508_10305_amd import synth
+    host = synth.clusters(150_001, seed=31, extra_fields=1)
+    dev = to_dev(host)
+    n, F = host[0].size, len(host)
+    eb = orc.rel_ebs(host, 1e-3)
+    s, perm = gpz.compress(dev, eb, want_perm=True)
+    out = gpz.decompress(s, n, F)
+    ws = gpz.stats_workspace(F)
+    monkeypatch.setenv("GPZ_FAULT", "alloc")
+    say("[case] reporting calls with GPZ_FAULT=alloc")
+    assert (gpz.rel_ebs(dev, 1e-3, ws=ws).view(np.uint32) == eb.view(np.uint32)).all()
+    st = gpz.error_stats(dev, out, eb, perm=perm, ws=ws)
+    v, m = gpz.bound_check(dev, out, eb, perm=perm, ws=ws)
+    pp = perm.cpu().numpy().astype(np.uint32)
+    ref_out = orc.decompress(s.cpu().numpy(), n, F)
+    rv, rm = orc.bound_check(host, ref_out, eb, perm=pp)
+    assert (v == rv).all() and (m == rm).all()
+    assert (st["violations"] == rv).all() and (st["max_abs_err"] == rm).all()
+    got = gpz.stream_stats(s, n, F, ws=ws)
+    ref = orc.stream_stats(s.cpu().numpy(), n, F)
+    assert got[0].tolist() == ref[0].tolist() and got[1] == ref[1]
+    for call in (lambda: gpz.field_range(dev), lambda: gpz.error_stats(dev, out, eb, perm=perm),
+                 lambda: gpz.bound_check(dev, out, eb), lambda: gpz.stream_stats(s, n, F)):
+        with pytest.raises(gpz.GpzError) as e:
+            call()
+        assert e.value.code == gpz.GPZ_ENOMEM
 
 
 def test_stream_stats_parity(gpz, orc):
