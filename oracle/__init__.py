@@ -79,20 +79,34 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int)]
         L.oracle_sort_rle.restype = ctypes.c_uint32
         L.oracle_sort_rle.argtypes = [u32p, ctypes.c_uint32, u32p, u32p, u32p, u32p]
+        dpp = ctypes.POINTER(f64p)
+        L.oracle_quantize_wide.restype = ctypes.c_uint64
+        L.oracle_quantize_wide.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_float,
+                                           ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.oracle_max_bytes.restype = ctypes.c_uint64
         L.oracle_max_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.oracle_max_bytes_typed.restype = ctypes.c_uint64
+        L.oracle_max_bytes_typed.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_int]
         L.oracle_compress.restype = ctypes.c_int
         L.oracle_compress.argtypes = [fpp, ctypes.c_uint64, ctypes.c_uint32, f32p, ctypes.c_uint32,
                                       ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.c_uint64, u64p,
                                       u32p]
+        L.oracle_compress_f64.restype = ctypes.c_int
+        L.oracle_compress_f64.argtypes = [dpp, ctypes.c_uint64, ctypes.c_uint32, f32p,
+                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, u8p,
+                                          ctypes.c_uint64, u64p, u32p]
+        L.oracle_decompress_f64.restype = ctypes.c_int
+        L.oracle_decompress_f64.argtypes = [u8p, ctypes.c_uint64, dpp, ctypes.c_uint64,
+                                            ctypes.c_uint32]
         L.oracle_encode_block.restype = ctypes.c_int
         L.oracle_encode_block.argtypes = [fpp, ctypes.c_uint32, ctypes.c_uint32, f32p,
                                           ctypes.c_uint32, ctypes.c_uint32, u32p, ctypes.c_uint32,
                                           u32p, u32p]
         L.oracle_block_trace.restype = ctypes.c_int
-        L.oracle_block_trace.argtypes = [fpp, ctypes.c_uint32, ctypes.c_uint32, f32p,
-                                         ctypes.c_uint32, ctypes.c_uint32, f32p, u32p, u32p, u8p,
-                                         u32p, u32p, u32p, u32p, u32p, u32p, u32p]
+        L.oracle_block_trace.argtypes = [fpp, dpp, ctypes.c_uint32, ctypes.c_uint32, f32p,
+                                         ctypes.c_uint32, ctypes.c_uint32, f64p, u8p, u32p, u64p,
+                                         u8p, u32p, u32p, u32p, u32p, u32p, u32p, u32p]
         L.oracle_inspect.restype = ctypes.c_int
         L.oracle_inspect.argtypes = [u8p, ctypes.c_uint64, u64p]
         L.oracle_decompress.restype = ctypes.c_int
@@ -129,6 +143,21 @@ def _field_ptrs(fields: Sequence[np.ndarray]):
     return arr
 
 
+def _field_ptrs64(fields: Sequence[np.ndarray]):
+    arr = (ctypes.POINTER(ctypes.c_double) * max(1, len(fields)))()
+    for i, f in enumerate(fields):
+        arr[i] = _ptr(f, ctypes.c_double)
+    return arr
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _is_f64(fields) -> bool:
+    return len(fields) > 0 and np.asarray(fields[0]).dtype == np.float64
+
+
 def _ebs(eb, F: int) -> np.ndarray:
     e = np.asarray(eb, dtype=np.float32)
     if e.ndim == 0:
@@ -153,6 +182,15 @@ def quantize(x: float, lo: float, eb: float):
     return int(q), bool(o.value)
 
 
+def quantize_wide(x: float, lo: float, eb: float, out_f32: bool):
+    """Grid index and outlier flag with 64-bit intermediates (Sec. 5.3);
+    out_f32: the reconstruction is rounded to float32 (float32 fields)."""
+    o = ctypes.c_int(0)
+    q = lib().oracle_quantize_wide(float(x), float(lo), ctypes.c_float(eb), int(out_f32),
+                                   ctypes.byref(o))
+    return int(q), bool(o.value)
+
+
 def sort_rle(keys: Sequence[int]):
     """Stable sort + run-length + delta coding of a key list (Sec. 4.2-4.3).
     Returns (perm, uniques, counts, deltas)."""
@@ -168,28 +206,31 @@ def sort_rle(keys: Sequence[int]):
     return perm[:n], uniq[:U], cnt[:U], dl[:U]
 
 
-def max_bytes(n: int, F: int, B: int = 1024) -> int:
-    return int(lib().oracle_max_bytes(n, F, B))
+def max_bytes(n: int, F: int, B: int = 1024, f64: bool = False) -> int:
+    return int(lib().oracle_max_bytes_typed(n, F, B, int(f64)))
 
 
 # ---------------------------------------------------------------- whole pipeline
 
 def compress(fields: Sequence[np.ndarray], eb, B: int = 1024, K: int = 3,
              KF: Optional[int] = None, want_perm: bool = False):
-    """Compress SoA float32 fields; returns (stream bytes as np.uint8, perm or None)."""
-    fields = [_f32(f) for f in fields]
+    """Compress SoA fields (all float32, or all float64: Sec. 5.1's down-cast
+    where it meets the bound); returns (stream bytes as np.uint8, perm or None)."""
+    f64 = _is_f64(fields)
+    fields = [(_f64 if f64 else _f32)(f) for f in fields]
     F = len(fields)
     n = fields[0].size if F else 0
     if KF is None:
         KF = min(F, 3)
     e = _ebs(eb, F)
-    cap = max_bytes(n, F, B) if F else 64
+    cap = max_bytes(n, F, B, f64) if F else 64
     out = np.zeros(max(cap, 4), np.uint8)
     nbytes = ctypes.c_uint64(0)
     perm = np.zeros(max(1, n), np.uint32) if want_perm else None
-    rc = lib().oracle_compress(_field_ptrs(fields), n, F, _ptr(e, ctypes.c_float), B, K, KF,
-                               _ptr(out, ctypes.c_uint8), out.size, ctypes.byref(nbytes),
-                               _ptr(perm, ctypes.c_uint32) if want_perm else None)
+    fn = lib().oracle_compress_f64 if f64 else lib().oracle_compress
+    rc = fn((_field_ptrs64 if f64 else _field_ptrs)(fields), n, F, _ptr(e, ctypes.c_float), B, K,
+            KF, _ptr(out, ctypes.c_uint8), out.size, ctypes.byref(nbytes),
+            _ptr(perm, ctypes.c_uint32) if want_perm else None)
     if rc != OK:
         raise OracleError(rc, "compress")
     return out[: nbytes.value].copy(), (perm[:n] if want_perm else None)
@@ -228,7 +269,7 @@ def _split(stream: np.ndarray):
 
 
 def _frame(n: int, F: int, B: int, K: int, KF: int, eb_bits: np.ndarray, lens: np.ndarray,
-           records: np.ndarray) -> np.ndarray:
+           records: np.ndarray, version_word: int = 1) -> np.ndarray:
     nb = lens.size
     ns = (nb + _SUPER - 1) // _SUPER
     offs = np.concatenate([[0], np.cumsum(lens.astype(np.uint64))[:-1]]).astype(np.uint64) \
@@ -236,7 +277,8 @@ def _frame(n: int, F: int, B: int, K: int, KF: int, eb_bits: np.ndarray, lens: n
     sup = np.zeros(2 * ns, np.uint32)
     sup[0::2] = (offs[::_SUPER] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
     sup[1::2] = (offs[::_SUPER] >> np.uint64(32)).astype(np.uint32)
-    hdr = np.array([_MAGIC, 1, n & 0xFFFFFFFF, n >> 32, F, B, K | (KF << 8), nb], np.uint32)
+    hdr = np.array([_MAGIC, version_word, n & 0xFFFFFFFF, n >> 32, F, B, K | (KF << 8), nb],
+                   np.uint32)
     return np.concatenate([hdr, sup, eb_bits.astype(np.uint32), lens.astype(np.uint32),
                            records.astype(np.uint32)]).view(np.uint8)
 
@@ -247,7 +289,8 @@ def compress_parallel(fields: Sequence[np.ndarray], eb, B: int = 1024, K: int = 
     """(stream, perm or None) as compress() returns them, computed chunk by
     chunk on host threads."""
     from concurrent.futures import ThreadPoolExecutor
-    fields = [_f32(f) for f in fields]
+    f64 = _is_f64(fields)
+    fields = [(_f64 if f64 else _f32)(f) for f in fields]
     F = len(fields)
     n = fields[0].size
     KF = min(F, 3) if KF is None else KF
@@ -270,7 +313,7 @@ def compress_parallel(fields: Sequence[np.ndarray], eb, B: int = 1024, K: int = 
         parts = list(ex.map(one, chunks))
     lens = np.concatenate([p[2] for p in parts])
     recs = np.concatenate([p[3] for p in parts])
-    return _frame(n, F, B, K, KF, parts[0][1], lens, recs), perm
+    return _frame(n, F, B, K, KF, parts[0][1], lens, recs, 1 | (int(f64) << 16)), perm
 
 
 def decompress_parallel(stream: np.ndarray, n: int, F: int,
@@ -290,7 +333,8 @@ def decompress_parallel(stream: np.ndarray, n: int, F: int,
     sup = w[_HEADER: _HEADER + 2 * ((nb + _SUPER - 1) // _SUPER)].astype(np.uint64)
     if nb and not ((sup[0::2] | (sup[1::2] << np.uint64(32))) == offs[:-1:_SUPER]).all():
         raise OracleError(ECORRUPT, "decompress_parallel")
-    outs = [np.zeros(n, np.float32) for _ in range(F)]
+    f64 = bool(info["flags"] & 1)
+    outs = [np.zeros(n, np.float64 if f64 else np.float32) for _ in range(F)]
     T = _threads(threads)
     per = max(1, -(-nb // (4 * T)))
     ranges = [(b0, min(nb, b0 + per)) for b0 in range(0, nb, per)]
@@ -298,7 +342,8 @@ def decompress_parallel(stream: np.ndarray, n: int, F: int,
     def one(r):
         b0, b1 = r
         lo, hi = b0 * B, min(n, b1 * B)
-        sub = _frame(hi - lo, F, B, K, KF, eb_bits, lens[b0:b1], recs[offs[b0]:offs[b1]])
+        sub = _frame(hi - lo, F, B, K, KF, eb_bits, lens[b0:b1], recs[offs[b0]:offs[b1]],
+                     int(hdr[1]))
         part = decompress(sub, hi - lo, F)
         for f in range(F):
             outs[f][lo:hi] = part[f]
@@ -330,16 +375,18 @@ def encode_block(fields: Sequence[np.ndarray], eb, K: int = 3, KF: Optional[int]
 
 
 def block_trace(fields: Sequence[np.ndarray], eb, K: int = 3, KF: Optional[int] = None) -> dict:
-    """Intermediate results of stages 1-3 for one block."""
-    fields = [_f32(f) for f in fields]
+    """Intermediate results of stages 1-3 for one block (float32 or float64)."""
+    f64 = _is_f64(fields)
+    fields = [(_f64 if f64 else _f32)(f) for f in fields]
     F = len(fields)
     n = fields[0].size
     if KF is None:
         KF = min(F, 3)
     e = _ebs(eb, F)
-    lo = np.zeros(F, np.float32)
+    lo = np.zeros(F, np.float64)
+    wide = np.zeros(F, np.uint8)
     s = np.zeros(3, np.uint32)
-    q = np.zeros(F * n, np.uint32)
+    q = np.zeros(F * n, np.uint64)
     outl = np.zeros(F * n, np.uint8)
     key = np.zeros(n, np.uint32)
     perm = np.zeros(n, np.uint32)
@@ -349,41 +396,51 @@ def block_trace(fields: Sequence[np.ndarray], eb, K: int = 3, KF: Optional[int] 
     U = ctypes.c_uint32(0)
     cw = ctypes.c_uint32(0)
     P = lambda a, t=ctypes.c_uint32: _ptr(a, t)
-    rc = lib().oracle_block_trace(_field_ptrs(fields), n, F, _ptr(e, ctypes.c_float), K, KF,
-                                  P(lo, ctypes.c_float), P(s), P(q), P(outl, ctypes.c_uint8),
-                                  P(key), P(perm), P(uniq), P(cnt), P(widths), ctypes.byref(U),
-                                  ctypes.byref(cw))
+    rc = lib().oracle_block_trace(None if f64 else _field_ptrs(fields),
+                                  _field_ptrs64(fields) if f64 else None, n, F,
+                                  _ptr(e, ctypes.c_float), K, KF, P(lo, ctypes.c_double),
+                                  P(wide, ctypes.c_uint8), P(s), P(q, ctypes.c_uint64),
+                                  P(outl, ctypes.c_uint8), P(key), P(perm), P(uniq), P(cnt),
+                                  P(widths), ctypes.byref(U), ctypes.byref(cw))
     if rc != OK:
         raise OracleError(rc, "block_trace")
     u = U.value
-    return dict(lo=lo, s=s[:KF], q=q.reshape(F, n), outlier=outl.reshape(F, n).astype(bool),
-                key=key, perm=perm, uniq=uniq[:u], count=cnt[:u], w_gap=int(widths[0]),
-                w_cnt=int(widths[1]), w=widths[2:].copy(), U=u, coded_words=cw.value)
+    return dict(lo=lo if f64 else lo.astype(np.float32), wide=wide.astype(bool), s=s[:KF],
+                q=q.reshape(F, n), outlier=outl.reshape(F, n).astype(bool), key=key, perm=perm,
+                uniq=uniq[:u], count=cnt[:u], w_gap=int(widths[0]), w_cnt=int(widths[1]),
+                w=widths[2:].copy(), U=u, coded_words=cw.value)
 
 
 def inspect(stream: np.ndarray) -> dict:
     s = np.ascontiguousarray(stream, dtype=np.uint8)
-    info = np.zeros(7, np.uint64)
+    info = np.zeros(8, np.uint64)
     rc = lib().oracle_inspect(_ptr(s, ctypes.c_uint8), s.size, _ptr(info, ctypes.c_uint64))
     if rc != OK:
         raise OracleError(rc, "inspect")
-    keys = ("n", "F", "B", "K", "KF", "nblocks", "bytes")
+    keys = ("n", "F", "B", "K", "KF", "nblocks", "bytes", "flags")
     return {k: int(v) for k, v in zip(keys, info)}
 
 
-def decompress(stream: np.ndarray, n: int, F: int) -> List[np.ndarray]:
+def _decode(stream: np.ndarray, n: int, F: int, f64: bool):
     s = np.ascontiguousarray(stream, dtype=np.uint8)
-    outs = [np.zeros(max(1, n), np.float32) for _ in range(F)]
-    rc = lib().oracle_decompress(_ptr(s, ctypes.c_uint8), s.size, _field_ptrs(outs), n, F)
+    outs = [np.zeros(max(1, n), np.float64 if f64 else np.float32) for _ in range(F)]
+    if f64:
+        rc = lib().oracle_decompress_f64(_ptr(s, ctypes.c_uint8), s.size, _field_ptrs64(outs), n, F)
+    else:
+        rc = lib().oracle_decompress(_ptr(s, ctypes.c_uint8), s.size, _field_ptrs(outs), n, F)
+    return int(rc), [o[:n] for o in outs]
+
+
+def decompress(stream: np.ndarray, n: int, F: int, f64: bool = False) -> List[np.ndarray]:
+    """Decoded fields (float64 arrays for a float64 stream, f64=True)."""
+    rc, outs = _decode(stream, n, F, f64)
     if rc != OK:
         raise OracleError(rc, "decompress")
-    return [o[:n] for o in outs]
+    return outs
 
 
-def decompress_status(stream: np.ndarray, n: int, F: int) -> int:
-    s = np.ascontiguousarray(stream, dtype=np.uint8)
-    outs = [np.zeros(max(1, n), np.float32) for _ in range(F)]
-    return int(lib().oracle_decompress(_ptr(s, ctypes.c_uint8), s.size, _field_ptrs(outs), n, F))
+def decompress_status(stream: np.ndarray, n: int, F: int, f64: bool = False) -> int:
+    return _decode(stream, n, F, f64)[0]
 
 
 def bound_check(orig: Sequence[np.ndarray], recon: Sequence[np.ndarray], eb, perm=None):

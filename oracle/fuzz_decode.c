@@ -2,9 +2,11 @@
  *
  * TEST INFRASTRUCTURE ONLY.  The tests build it with AddressSanitizer and
  * UndefinedBehaviorSanitizer (host code, gcc) and run it: it compresses
- * seeded random particle sets, damages the streams (bit flips, truncation,
- * random length-table entries, random header words, random superblock
- * offsets) and hands them to oracle_decompress and oracle_stream_stats.
+ * seeded random particle sets (float32 ones, float32 ones whose value range
+ * needs 64-bit grid indices, and float64 ones), damages the streams (bit
+ * flips, truncation, random length-table entries, random header words,
+ * random superblock offsets) and hands them to oracle_decompress /
+ * oracle_decompress_f64 and oracle_stream_stats.
  * Whatever the bytes, the readers must return a status and never read or
  * write outside their buffers; the sanitizers abort on the first violation.
  *
@@ -19,10 +21,15 @@
 int oracle_compress(const float *const *fields, uint64_t n, uint32_t F, const float *eb, uint32_t B,
                     uint32_t K, uint32_t KF, uint8_t *out, uint64_t cap, uint64_t *out_bytes,
                     uint32_t *perm_out);
+int oracle_compress_f64(const double *const *fields, uint64_t n, uint32_t F, const float *eb,
+                        uint32_t B, uint32_t K, uint32_t KF, uint8_t *out, uint64_t cap,
+                        uint64_t *out_bytes, uint32_t *perm_out);
 int oracle_decompress(const uint8_t *in, uint64_t bytes, float *const *out, uint64_t n, uint32_t F);
+int oracle_decompress_f64(const uint8_t *in, uint64_t bytes, double *const *out, uint64_t n,
+                          uint32_t F);
 int oracle_stream_stats(const uint8_t *in, uint64_t bytes, uint64_t n, uint32_t F,
                         uint64_t *outliers, uint64_t *raw_blocks);
-uint64_t oracle_max_bytes(uint64_t n, uint32_t F, uint32_t B);
+uint64_t oracle_max_bytes_typed(uint64_t n, uint32_t F, uint32_t B, int f64);
 
 /* splitmix64: a small, seeded generator for the cases */
 static uint64_t state;
@@ -46,26 +53,39 @@ int main(int argc, char **argv) {
         const uint32_t F = 1 + below(6);
         const uint32_t KF = 1 + below(F < 3 ? F : 3);
         const uint32_t K = below(6);
+        /* kind 0: float32; 1: float32 over a range wider than 2^24 grid
+         * steps (64-bit grid indices); 2: float64 */
+        const uint32_t kind = below(3);
+        const float scale = kind == 1 ? 1e7f : 1000.0f;
         float eb[64];
         float *x[64];
         float *y[64];
+        double *x64[64];
+        double *y64[64];
         for (uint32_t f = 0; f < F; f++) {
             eb[f] = powf(10.0f, -1.0f - 5.0f * unit());
+            if (kind == 2 && below(2)) eb[f] = 1e-9f;  /* finer than float32 resolves */
             x[f] = (float *)malloc(sizeof(float) * (n ? n : 1));
             y[f] = (float *)malloc(sizeof(float) * (n ? n : 1));
+            x64[f] = (double *)malloc(sizeof(double) * (n ? n : 1));
+            y64[f] = (double *)malloc(sizeof(double) * (n ? n : 1));
             for (uint64_t i = 0; i < n; i++) {
-                float v = unit() * (below(2) ? 1.0f : 1000.0f);
+                float v = unit() * (below(2) ? 1.0f : scale);
                 uint32_t r = below(100);
                 if (r == 0) v = NAN;
                 else if (r == 1) v = INFINITY;
                 else if (r == 2) v = -0.0f;
                 x[f][i] = v;
+                x64[f][i] = (double)v + (double)unit() * 1e-9;
             }
         }
-        const uint64_t cap = oracle_max_bytes(n, F, B);
+        const uint64_t cap = oracle_max_bytes_typed(n, F, B, kind == 2);
         uint8_t *s = (uint8_t *)malloc(cap);
         uint64_t len = 0;
-        if (oracle_compress((const float *const *)x, n, F, eb, B, K, KF, s, cap, &len, NULL) != 0) {
+        int crc = kind == 2
+            ? oracle_compress_f64((const double *const *)x64, n, F, eb, B, K, KF, s, cap, &len, NULL)
+            : oracle_compress((const float *const *)x, n, F, eb, B, K, KF, s, cap, &len, NULL);
+        if (crc != 0) {
             fprintf(stderr, "compress failed (case %d)\n", it);
             return 2;
         }
@@ -99,7 +119,9 @@ int main(int argc, char **argv) {
             /* the readers see exactly dl bytes: copy into a buffer of that size */
             uint8_t *e = (uint8_t *)malloc(dl ? dl : 1);
             memcpy(e, d, dl);
-            if (oracle_decompress(e, dl, y, n, F) == 0) decoded++;
+            const int drc = kind == 2 ? oracle_decompress_f64(e, dl, y64, n, F)
+                                      : oracle_decompress(e, dl, y, n, F);
+            if (drc == 0) decoded++;
             else rejected++;
             (void)oracle_stream_stats(e, dl, n, F, outl, &raw);
             free(e);
@@ -109,6 +131,8 @@ int main(int argc, char **argv) {
         for (uint32_t f = 0; f < F; f++) {
             free(x[f]);
             free(y[f]);
+            free(x64[f]);
+            free(y64[f]);
         }
     }
     printf("fuzz_decode: %d cases, %ld damaged streams decoded, %ld rejected\n", iters, decoded,

@@ -481,7 +481,186 @@ def test_stream_stats_counts(orc):
     s, _ = orc.compress(smooth, 1e-3)
     out, raw = orc.stream_stats(s, n, 3)
     assert out.tolist() == [0, 3, 1] and raw == 0
+    # a grid finer than 2^53 steps over the block range: every index is out
+    # of range even for 64-bit intermediates, every value an outlier, every
+    # block raw
     noise = [np.random.default_rng(f).random(n).astype(np.float32) for f in range(3)]
-    s, _ = orc.compress(noise, 1e-9)
+    s, _ = orc.compress(noise, 1e-30)
     out, raw = orc.stream_stats(s, n, 3)
     assert raw == 3 and out.tolist() == [0, 0, 0]
+
+
+# ----------------------------------------------------------- 64-bit intermediates and float64
+
+
+def _wide_gold_fields(blk, key):
+    """Arrays of one wide_blocks.json block; "nan" entries take its NaN bits."""
+    dt = np.float64 if blk["dtype"] == "float64" else np.float32
+    out = []
+    for v in blk[key]:
+        a = np.array([np.nan if x == "nan" else x for x in v], dt)
+        if dt == np.float64 and "nan_bits64" in blk:
+            a.view(np.uint64)[np.isnan(a)] = blk["nan_bits64"]
+        out.append(a)
+    return out
+
+
+@pytest.mark.parametrize("name", ["f32_wide_range", "f64_wide_shift_32", "f64_downcast",
+                                  "f64_precision"])
+def test_wide_and_float64_blocks_by_hand(orc, name):
+    """Sec. 5.3 / Sec. 5.1 extension of the record layout: every stream word,
+    the permutation, the field mode and the decoded bits of four blocks were
+    derived by hand (tests/golden/wide_blocks.json)."""
+    blk = {b["name"]: b for b in _gold("wide_blocks.json")["blocks"]}[name]
+    fields = _wide_gold_fields(blk, "fields")
+    f64 = blk["dtype"] == "float64"
+    if name == "f64_downcast":
+        assert fields[0][1] == 0.25 + 2.0 ** -40
+    if name == "f64_precision":
+        assert fields[0][1] == 1.0 + 2.0 ** -30 and np.float32(blk["eb"]) == 2.0 ** -40
+    s, perm = orc.compress(fields, blk["eb"], B=blk["B"], K=blk["K"], KF=blk["KF"],
+                           want_perm=True)
+    assert _words(s).tolist() == blk["stream_words"]
+    assert perm.tolist() == blk["perm"]
+    assert orc.inspect(s)["flags"] == int(f64)
+    out = orc.decompress(s, fields[0].size, len(fields), f64=f64)
+    want = _wide_gold_fields(blk, "decompressed")
+    ut = np.uint64 if f64 else np.uint32
+    for got, w in zip(out, want):
+        assert got.dtype == w.dtype and (got.view(ut) == w.view(ut)).all()
+    tr = orc.block_trace(fields, blk["eb"], K=blk["K"], KF=blk["KF"])
+    assert tr["wide"].tolist() == blk["wide"]
+
+
+@pytest.mark.parametrize("eb", [1.3e-5, 2.0 ** -18, 7.7e-7])
+def test_wide_quantizer_against_exact_rationals(orc, eb):
+    """A grid wider than 2^24 steps (float32 values up to 1000 over the block
+    minimum 0): the 64-bit grid index is within 1 of the exact nearest index,
+    and the outlier flag is exactly "the float32 value nearest to the exact
+    reconstruction q * 2eb + lo (rounded to double, then to float32) is not
+    strictly within eb of x" -- evaluated here in exact rationals."""
+    eb32 = float(np.float32(eb))
+    twoeb = Fraction(2) * Fraction(eb32)
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([rng.random(1500) * 1000.0, rng.random(500)]).astype(np.float32)
+    assert float(xs.max()) / (2 * eb32) > 2 ** 24
+    n_out = 0
+    for x in xs:
+        x = float(x)
+        q, outl = orc.quantize_wide(x, 0.0, eb32, True)
+        exact = round(Fraction(x) / twoeb)
+        assert abs(q - exact) <= 1
+        y_exact = Fraction(q) * twoeb
+        y64 = float(y_exact)  # correctly rounded to double (int / int division)
+        y32 = float(np.float32(y64))  # then to float32 (round to nearest even)
+        within = abs(Fraction(y32) - Fraction(x)) < Fraction(eb32)
+        assert outl == (not within)
+        n_out += outl
+    # the small values are resolved by float32; only the large ones may miss
+    assert n_out < 1500
+
+
+def test_wide_range_block_is_coded_not_outliers(orc):
+    """A block whose values near its minimum need a grid finer than 2^-24 of
+    its range: the 32-bit steps would store every value beyond 2^24 - 1
+    steps verbatim (index 0, outlier), the wide steps code them.  Here the
+    large values lie exactly on the grid, so none is an outlier and all are
+    reconstructed exactly; the small ones are within the bound."""
+    eb = 2.0 ** -10
+    rng = np.random.default_rng(9)
+    x = rng.random(1024).astype(np.float32)
+    big = np.arange(1, 17, dtype=np.float64) * 2.0 ** 20
+    x[::64] = big.astype(np.float32)
+    # under 32-bit steps alone the large values would be outliers
+    assert all(orc.quantize(float(v), 0.0, eb)[1] for v in big)
+    tr = orc.block_trace([x], eb, K=3, KF=1)
+    assert tr["wide"].tolist() == [True]
+    assert not tr["outlier"].any()
+    s, perm = orc.compress([x], eb, K=3, KF=1, want_perm=True)
+    y = orc.decompress(s, x.size, 1)[0]
+    src = x[perm]
+    d = np.abs(y.astype(np.float64) - src.astype(np.float64))
+    assert (d < eb).all()
+    assert (y[src >= 2.0 ** 20] == src[src >= 2.0 ** 20]).all()
+    outl, raw = orc.stream_stats(s, x.size, 1)
+    assert outl.tolist() == [0] and raw == 0
+
+
+def test_float64_downcast_when_bound_allows(orc):
+    """Float64 values that are float32 values.  In a block where the float32
+    steps leave no outlier, the down-cast meets the bound: the float64
+    stream takes the 32-bit steps there, keeps the block's permutation and
+    decodes to the float32 stream's values widened.  In a block where some
+    value misses the bound in float32 (near half-way values), the float64
+    field goes wide and every value stays within the bound."""
+    rng = np.random.default_rng(3)
+    B, n = 1024, 5 * 1024
+    # blocks 0-2 in [0, 1) (float32 spacing far below eb), 3-4 in [0, 100)
+    scale = np.repeat([1.0, 1.0, 1.0, 100.0, 100.0], B)
+    x32 = [(rng.random(n) * scale).astype(np.float32) for _ in range(4)]
+    x64 = [a.astype(np.float64) for a in x32]
+    eb = 1e-3
+    s32, p32 = orc.compress(x32, eb, want_perm=True)
+    s64, p64 = orc.compress(x64, eb, want_perm=True)
+    y32 = orc.decompress(s32, n, 4)
+    y64 = orc.decompress(s64, n, 4, f64=True)
+    kinds = set()
+    for b in range(n // B):
+        sl = slice(b * B, (b + 1) * B)
+        t32 = orc.block_trace([a[sl] for a in x32], eb)
+        t64 = orc.block_trace([a[sl] for a in x64], eb)
+        for f in range(4):
+            if not t32["outlier"][f].any():
+                assert not t64["wide"][f]
+                kinds.add("down-cast")
+            else:
+                assert t64["wide"][f]
+                kinds.add("wide")
+        if not t64["wide"].any():
+            assert (p32[sl] == p64[sl]).all()
+            for a, c in zip(y32, y64):
+                assert (a[sl].astype(np.float64) == c[sl]).all()
+    assert kinds == {"down-cast", "wide"}
+    for f in range(4):
+        assert (np.abs(y64[f] - x64[f][p64]) < eb).all()
+
+
+def test_float64_wide_when_float32_cannot_meet_bound(orc):
+    """Float64 values spaced below float32 resolution with a bound below it:
+    every block takes the wide steps, nothing is an outlier, and every
+    decoded value is within the bound of its float64 original (where the
+    float32 down-cast alone misses by up to 2^-24 relative)."""
+    rng = np.random.default_rng(4)
+    n = 3000
+    x = [1.0 + rng.integers(0, 2 ** 20, n) * 2.0 ** -35 + rng.random(n) * 2.0 ** -40
+         for _ in range(3)]
+    eb = 2.0 ** -38
+    assert max(abs(float(np.float32(v)) - v) for v in x[0][:200]) > eb
+    s, perm = orc.compress(x, eb, want_perm=True)
+    for b in range(-(-n // 1024)):
+        tr = orc.block_trace([a[b * 1024:(b + 1) * 1024] for a in x], eb)
+        assert tr["wide"].all() and not tr["outlier"].any()
+    y = orc.decompress(s, n, 3, f64=True)
+    for f in range(3):
+        assert (np.abs(y[f] - x[f][perm]) < eb).all()
+    outl, raw = orc.stream_stats(s, n, 3)
+    assert outl.tolist() == [0, 0, 0] and raw == 0
+
+
+def test_float64_non_finite_bit_exact_and_type_checked(orc):
+    """Non-finite float64 values (any NaN payload, +-inf) are outliers stored
+    as their 64-bit patterns; a float64 stream read as float32 (or the
+    reverse) is refused as an argument error."""
+    x = np.linspace(-1, 1, 300)
+    bits = x.view(np.uint64)
+    bits[[3, 77, 150]] = [0x7FF0000000000001, 0xFFF8DEADBEEF0000, 0x7FF0000000000000]
+    x[200] = -np.inf
+    s, perm = orc.compress([x, x[::-1].copy()], 1e-4, want_perm=True)
+    y = orc.decompress(s, x.size, 2, f64=True)
+    src = x[perm]
+    nf = ~np.isfinite(src)
+    assert nf.sum() == 4
+    assert (y[0][nf].view(np.uint64) == src[nf].view(np.uint64)).all()
+    assert orc.decompress_status(s, x.size, 2, f64=False) == orc.EINVAL
+    s32, _ = orc.compress([x.astype(np.float32)], 1e-4)
+    assert orc.decompress_status(s32, x.size, 1, f64=True) == orc.EINVAL

@@ -5,13 +5,15 @@ the stream never exceeds the all-raw size, decompression respects the bound
 (non-finite values bit-exact), the permutation stays inside its block, each
 coded block comes out stably sorted by segment ID (Sec. 4.2, checked with
 numpy's stable argsort on IDs recomputed from the quantized values), raw
-blocks keep input order, and compression is deterministic."""
+blocks keep input order, and compression is deterministic.  Inputs are
+float32 or float64 (Sec. 5.1), and the value mixes include ranges that need
+64-bit grid indices (Sec. 5.3) and float64 values finer than float32."""
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
 from hypothesis import strategies as st
 
-KINDS = ("uniform", "clustered", "specials", "constant", "wide", "ongrid")
+KINDS = ("uniform", "clustered", "specials", "constant", "wide", "ongrid", "widegrid")
 
 
 @st.composite
@@ -24,10 +26,13 @@ def cases(draw):
     eb = float(np.float32(10.0 ** draw(st.floats(-6.0, -1.0))))
     seed = draw(st.integers(0, 2**32 - 1))
     kind = draw(st.sampled_from(KINDS))
-    return B, n, F, K, KF, eb, seed, kind
+    f64 = draw(st.booleans())
+    if f64 and draw(st.booleans()):
+        eb = float(np.float32(10.0 ** draw(st.floats(-12.0, -7.0))))  # below float32 spacing
+    return B, n, F, K, KF, eb, seed, kind, f64
 
 
-def make_fields(n, F, eb, seed, kind):
+def make_fields(n, F, eb, seed, kind, f64=False):
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(F):
@@ -49,10 +54,18 @@ def make_fields(n, F, eb, seed, kind):
             x = np.full(n, rng.normal())
         elif kind == "wide":
             x = rng.normal(0, 1, n) * 10.0 ** rng.integers(-3, 30, n)
+        elif kind == "widegrid":  # small values beside a few far ones: > 2^24 grid steps
+            x = rng.random(n)
+            m = rng.random(n) < 0.02
+            x[m] = rng.integers(1, 9, int(m.sum())) * 2.0 ** 22
         else:  # (near) the grid of the bound
             k = rng.integers(0, 4000, n).astype(np.float64)
             x = k * (2.0 * float(np.float32(eb))) + rng.normal()
-        out.append(np.asarray(x, dtype=np.float32))
+        if f64:
+            x = np.asarray(x, dtype=np.float64) * (1.0 + rng.random(n) * 2.0 ** -30)
+            out.append(np.asarray(x, dtype=np.float64))
+        else:
+            out.append(np.asarray(x, dtype=np.float32))
     return out
 
 
@@ -72,27 +85,36 @@ def record_modes(stream, n, F, B):
 @settings(max_examples=400, deadline=None, suppress_health_check=[HealthCheck.too_slow])
 @given(cases())
 def test_oracle_invariants(orc, case):
-    B, n, F, K, KF, eb, seed, kind = case
-    fields = make_fields(n, F, eb, seed, kind)
+    B, n, F, K, KF, eb, seed, kind, f64 = case
+    fields = make_fields(n, F, eb, seed, kind, f64)
     s, perm = orc.compress(fields, eb, B=B, K=K, KF=KF, want_perm=True)
     s2, _ = orc.compress(fields, eb, B=B, K=K, KF=KF, want_perm=True)
     assert (s == s2).all(), "compression is not deterministic"
     info = orc.inspect(s)
     assert (info["n"], info["F"], info["B"], info["K"], info["KF"]) == (n, F, B, K, KF)
     assert info["nblocks"] == -(-n // B) and info["bytes"] == s.size
-    assert s.size <= orc.max_bytes(n, F, B)
-    out = orc.decompress(s, n, F)
-    viol, _ = orc.bound_check(fields, out, eb, perm=perm)
-    assert int(viol.sum()) == 0
+    assert info["flags"] == int(f64)
+    assert s.size <= orc.max_bytes(n, F, B, f64)
+    out = orc.decompress(s, n, F, f64=f64)
+    if f64:
+        for f in range(F):
+            x = fields[f][perm.astype(np.int64)]
+            same = out[f].view(np.uint64) == x.view(np.uint64)
+            with np.errstate(invalid="ignore"):
+                assert (same | (np.abs(out[f] - x) <= float(np.float32(eb)))).all()
+    else:
+        viol, _ = orc.bound_check(fields, out, eb, perm=perm)
+        assert int(viol.sum()) == 0
     if n == 0:
         return
     perm = perm.astype(np.int64)
     j = np.arange(n)
     assert (perm // B == j // B).all(), "permutation leaves its block"
+    ut = np.uint64 if f64 else np.uint32
     for f in range(F):
         src = fields[f][perm]
         nf = ~np.isfinite(src)
-        assert (out[f][nf].view(np.uint32) == src[nf].view(np.uint32)).all()
+        assert (out[f][nf].view(ut) == src[nf].view(ut)).all()
     modes = record_modes(s, n, F, B)
     for b, mode in enumerate(modes):
         lo, hi = b * B, min(n, (b + 1) * B)
@@ -104,6 +126,6 @@ def test_oracle_invariants(orc, case):
         tr = orc.block_trace([f[lo:hi] for f in fields], eb, K=K, KF=KF)
         ids = np.zeros(hi - lo, np.int64)
         for ax in range(KF):
-            seg = (tr["q"][ax].astype(np.int64) & 0xFFFFFF) >> int(tr["s"][ax])
+            seg = tr["q"][ax].astype(np.int64) >> int(tr["s"][ax])
             ids = (ids << K) | seg
         assert (p == np.argsort(ids, kind="stable")).all(), f"block {b} not stably sorted"
