@@ -313,7 +313,10 @@ def compress_parallel(fields: Sequence[np.ndarray], eb, B: int = 1024, K: int = 
         parts = list(ex.map(one, chunks))
     lens = np.concatenate([p[2] for p in parts])
     recs = np.concatenate([p[3] for p in parts])
-    return _frame(n, F, B, K, KF, parts[0][1], lens, recs, 1 | (int(f64) << 16)), perm
+    flags = 0
+    for p in parts:  # header flags of the whole stream: any chunk's
+        flags |= int(p[0][1]) >> 16
+    return _frame(n, F, B, K, KF, parts[0][1], lens, recs, 1 | (flags << 16)), perm
 
 
 def decompress_parallel(stream: np.ndarray, n: int, F: int,
@@ -343,7 +346,7 @@ def decompress_parallel(stream: np.ndarray, n: int, F: int,
         b0, b1 = r
         lo, hi = b0 * B, min(n, b1 * B)
         sub = _frame(hi - lo, F, B, K, KF, eb_bits, lens[b0:b1], recs[offs[b0]:offs[b1]],
-                     int(hdr[1]))
+                     int(hdr[1]))  # the whole stream's flags (a chunk may hold no wide record)
         part = decompress(sub, hi - lo, F)
         for f in range(F):
             outs[f][lo:hi] = part[f]

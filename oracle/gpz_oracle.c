@@ -33,7 +33,8 @@
 #define OR_SUPER 64u /* blocks per superblock offset entry */
 #define OR_QMAX 16777215.0f /* largest grid index: 2^24 - 1 */
 #define OR_QMAX_WIDE 9007199254740991.0 /* largest wide grid index: 2^53 - 1 */
-#define OR_FLAG_F64 1u /* stream flag (header word 1, bits 16+): float64 fields */
+#define OR_FLAG_F64 1u  /* stream flag (header word 1, bits 16+): float64 fields */
+#define OR_FLAG_WIDE 2u /* stream flag: some record holds a field coded with 64-bit steps */
 
 /* ------------------------------------------------------------------ */
 /* small helpers                                                        */
@@ -640,6 +641,7 @@ static int compress_impl(const float *const *f32, const double *const *f64, uint
     uint32_t *lens = (uint32_t *)calloc(nb + 1, sizeof(uint32_t));
     uint32_t **recs = (uint32_t **)calloc(nb + 1, sizeof(uint32_t *));
     uint64_t total = pre;
+    int any_wide = 0;
     for (uint64_t b = 0; b < nb; b++) {
         uint32_t nn = (uint32_t)((b + 1) * B <= n ? B : n - b * B);
         block_in in;
@@ -655,6 +657,7 @@ static int compress_impl(const float *const *f32, const double *const *f64, uint
         uint32_t cap_words = st.coded_words > rw ? st.coded_words : rw;
         recs[b] = (uint32_t *)calloc(cap_words, sizeof(uint32_t));
         lens[b] = write_block(&in, &st, recs[b]);
+        if (recs[b][0] >> 31) any_wide = 1;
         if (perm_out) {
             int raw = recs[b][0] == 1u;
             for (uint32_t p = 0; p < nn; p++) perm_out[b * B + p] = (uint32_t)(b * B + (raw ? p : st.perm[p]));
@@ -669,7 +672,7 @@ static int compress_impl(const float *const *f32, const double *const *f64, uint
     } else {
         uint32_t *w = (uint32_t *)malloc(4 * total);
         w[0] = OR_MAGIC;
-        w[1] = OR_VERSION | ((is64 ? OR_FLAG_F64 : 0u) << 16);
+        w[1] = OR_VERSION | (((is64 ? OR_FLAG_F64 : 0u) | (any_wide ? OR_FLAG_WIDE : 0u)) << 16);
         w[2] = (uint32_t)(n & 0xFFFFFFFFu);
         w[3] = (uint32_t)(n >> 32);
         w[4] = F;
@@ -701,7 +704,8 @@ static int compress_impl(const float *const *f32, const double *const *f64, uint
 }
 
 /* Stream layout (words, little-endian):
- *   0: magic "GPZ1"   1: version 1 | flags << 16 (flag 1: float64 fields)
+ *   0: magic "GPZ1"   1: version 1 | flags << 16 (flag 1: float64 fields;
+ *      flag 2: some record has a field coded with the 64-bit steps)
  *   2-3: N (u64)   4: F   5: B   6: K | KF << 8    7: number of blocks
  *   superblock table: one u64 per 64 blocks = word offset of the
  *                     superblock's first record inside the record area
@@ -815,7 +819,8 @@ static void out_raw(const block_out *o, uint32_t f, uint64_t i, const uint32_t *
 }
 
 static int decode_block(const uint32_t *rec, uint32_t len, uint32_t n, uint32_t F, uint32_t K,
-                        uint32_t KF, const float *eb, const block_out *y, uint64_t base) {
+                        uint32_t KF, const float *eb, const block_out *y, uint64_t base,
+                        int wide_allowed) {
     int f64 = y->y64 != NULL;
     uint32_t vw = value_words(f64);
     if (len < 1) return OR_ECORRUPT;
@@ -828,6 +833,9 @@ static int decode_block(const uint32_t *rec, uint32_t len, uint32_t n, uint32_t 
     }
     if (mode != 0 || len < 2) return OR_ECORRUPT;
     uint32_t U = (rec[0] & 0x7FFFFFFFu) >> 2, any_wide = rec[0] >> 31;
+    /* a stream announces wide records in its header (decoders may skip the
+     * search for them otherwise) */
+    if (any_wide && !wide_allowed) return OR_ECORRUPT;
     uint32_t h1 = rec[1];
     uint32_t w_gap = h1 & 31u, w_cnt = (h1 >> 5) & 31u;
     uint32_t s[3];
@@ -930,7 +938,8 @@ int oracle_inspect(const uint8_t *in, uint64_t bytes, uint64_t *info) {
     if (bytes < 4 * OR_HEADER_WORDS || bytes % 4 != 0) return OR_ECORRUPT;
     const uint32_t *w = (const uint32_t *)in;
     uint32_t flags = w[1] >> 16;
-    if (w[0] != OR_MAGIC || (w[1] & 0xFFFFu) != OR_VERSION || (flags & ~OR_FLAG_F64) != 0)
+    if (w[0] != OR_MAGIC || (w[1] & 0xFFFFu) != OR_VERSION ||
+        (flags & ~(OR_FLAG_F64 | OR_FLAG_WIDE)) != 0)
         return OR_ECORRUPT;
     uint64_t n = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
     uint32_t F = w[4], B = w[5], K = w[6] & 0xFFu, KF = (w[6] >> 8) & 0xFFu;
@@ -982,7 +991,8 @@ static int decompress_impl(const uint8_t *in, uint64_t bytes, const block_out *o
             if (so != off) return OR_ECORRUPT;
         }
         uint32_t nn = (uint32_t)((b + 1) * B <= n ? B : n - b * B);
-        rc = decode_block(rec + off, lt[b], nn, F, K, KF, eb, out, b * B);
+        rc = decode_block(rec + off, lt[b], nn, F, K, KF, eb, out, b * B,
+                          (info[7] & OR_FLAG_WIDE) != 0);
         if (rc) return rc;
         off += lt[b];
     }

@@ -522,7 +522,7 @@ def test_wide_and_float64_blocks_by_hand(orc, name):
                            want_perm=True)
     assert _words(s).tolist() == blk["stream_words"]
     assert perm.tolist() == blk["perm"]
-    assert orc.inspect(s)["flags"] == int(f64)
+    assert orc.inspect(s)["flags"] == int(f64) | (2 if any(blk["wide"]) else 0)
     out = orc.decompress(s, fields[0].size, len(fields), f64=f64)
     want = _wide_gold_fields(blk, "decompressed")
     ut = np.uint64 if f64 else np.uint32
@@ -530,6 +530,12 @@ def test_wide_and_float64_blocks_by_hand(orc, name):
         assert got.dtype == w.dtype and (got.view(ut) == w.view(ut)).all()
     tr = orc.block_trace(fields, blk["eb"], K=blk["K"], KF=blk["KF"])
     assert tr["wide"].tolist() == blk["wide"]
+    if any(blk["wide"]):
+        # a wide record in a stream that does not announce one is corrupt
+        bad = _words(s).copy()
+        bad[1] &= ~np.uint32(2 << 16)
+        assert orc.decompress_status(bad.view(np.uint8), fields[0].size, len(fields),
+                                     f64=f64) == orc.ECORRUPT
 
 
 @pytest.mark.parametrize("eb", [1.3e-5, 2.0 ** -18, 7.7e-7])

@@ -93,7 +93,7 @@ def test_oracle_invariants(orc, case):
     info = orc.inspect(s)
     assert (info["n"], info["F"], info["B"], info["K"], info["KF"]) == (n, F, B, K, KF)
     assert info["nblocks"] == -(-n // B) and info["bytes"] == s.size
-    assert info["flags"] == int(f64)
+    assert info["flags"] & 1 == int(f64)
     assert s.size <= orc.max_bytes(n, F, B, f64)
     out = orc.decompress(s, n, F, f64=f64)
     if f64:
