@@ -1,8 +1,8 @@
 /*
  * gpz.h -- C ABI of the MI355X (gfx950) GPZ particle compressor.
  *
- * GPZ (arXiv 2508.10305) compresses float32 particle fields under a
- * per-field absolute error bound: spatial quantization (Sec. 4.1), in-block
+ * GPZ (arXiv 2508.10305) compresses float32 (or float64, Sec. 5.1) particle
+ * fields under a per-field absolute error bound: spatial quantization (Sec. 4.1), in-block
  * sort by segment ID (Sec. 4.2), run-length + delta + fixed-length coding
  * (Sec. 4.3) and compaction of the block records by a prefix sum of their
  * sizes (Sec. 4.4).  Decompression reverses the steps without un-sorting
@@ -37,12 +37,15 @@ typedef enum {
     GPZ_ECORRUPT = -3,    /* compressed stream malformed or inconsistent with n / F */
     GPZ_EDEVICE = -4,     /* a HIP runtime call failed */
     GPZ_ENOMEM = -5,      /* the library could not allocate a workspace */
-    GPZ_EUNSUPPORTED = -6 /* valid stream/parameters this build has no kernel for */
+    GPZ_EUNSUPPORTED = -6 /* valid request this build has no kernel for (the single-pass
+                             compaction with float64 fields or a block size outside
+                             256..2048) */
 } gpz_status;
 
 /* Compression parameters.
- * block_size : particles per block B, power of two.  The format allows
- *              64..4096; the gfx950 kernels handle 256, 512, 1024, 2048.
+ * block_size : particles per block B, power of two, 64..4096.  256..2048
+ *              run one wave per block; the other sizes (and float64 fields)
+ *              run the generic kernels, one 256-lane workgroup per block.
  *              Default 1024 (32 threads x 32 points per block, Sec. 4.2).
  * seg_bits   : K, 0..5: each key axis is cut into 2^K power-of-two segments
  *              (segment size proportional to the block's range, Sec. 4.1).
@@ -51,7 +54,15 @@ typedef enum {
  *              coordinates whose segment IDs form the sort key.  Default
  *              min(F, 3).
  * flags      : 0 (default) or GPZ_FLAG_SINGLE_PASS.  Compression only; the
- *              stream is the same byte for byte either way.
+ *              stream is the same byte for byte either way, except that the
+ *              single pass stores raw a block that needs 64-bit grid steps.
+ *
+ * 64-bit steps (Sec. 5.3: 64-bit intermediates when the value range needs
+ * them): a float32 field of a block in which some finite value lies more than
+ * 2^24 - 1 grid steps (2 eb each) above the block minimum is quantized in
+ * double with grid indices up to 2^53 - 1, its reconstruction rounded to
+ * float32; otherwise grid indices stay below 2^24 and the arithmetic is
+ * float32.
  */
 typedef struct {
     uint32_t block_size;
@@ -66,6 +77,10 @@ typedef struct {
  * over the lengths of the earlier blocks (one launch fewer, no record copy,
  * but every block waits for the blocks before it; slower on MI355X). */
 #define GPZ_FLAG_SINGLE_PASS 1u
+
+/* Stream flags (gpz_info.flags; header word 1, bits 16 and up). */
+#define GPZ_STREAM_F64 1u  /* the fields are float64 */
+#define GPZ_STREAM_WIDE 2u /* some record holds a field coded with 64-bit steps */
 
 /* Fills *p with the defaults for F fields. */
 void gpz_default_params(gpz_params *p, uint32_t nfields);
@@ -110,13 +125,37 @@ int gpz_compress_async(const float *const *h_fields, uint64_t n, uint32_t nfield
                        uint64_t *d_out_bytes, uint32_t *d_perm, void *d_ws, uint64_t ws_bytes,
                        void *stream);
 
+/* Float64 fields (Sec. 5.1): as gpz_compress, with h_fields an array of F
+ * device pointers to n doubles and bounds still float32.  Each field of each
+ * block is down-cast to float32 and quantized by the float32 steps when every
+ * finite value is then reconstructed strictly within eb of its double
+ * (|y - x| < eb in double); otherwise it is quantized from the doubles with
+ * 64-bit steps (double arithmetic, grid indices up to 2^53 - 1).  Non-finite
+ * values are stored verbatim (64-bit patterns).  The stream carries
+ * GPZ_STREAM_F64 and decodes with gpz_decompress_f64 only.  Runs the generic
+ * kernels; GPZ_FLAG_SINGLE_PASS gives GPZ_EUNSUPPORTED.  Sizes:
+ * gpz_max_compressed_bytes_f64, gpz_compress_workspace_bytes_f64. */
+int gpz_compress_f64(const double *const *h_fields, uint64_t n, uint32_t nfields,
+                     const float *h_eb, const gpz_params *p, void *d_out, uint64_t out_capacity,
+                     uint64_t *h_out_bytes, uint32_t *d_perm, void *d_ws, uint64_t ws_bytes,
+                     void *stream);
+uint64_t gpz_max_compressed_bytes_f64(uint64_t n, uint32_t nfields, const gpz_params *p);
+uint64_t gpz_compress_workspace_bytes_f64(uint64_t n, uint32_t nfields, const gpz_params *p);
+
 /* Decompress a stream of in_bytes bytes (Sec. 3.2) into F device arrays of n
  * floats (h_fields_out: host array of F device pointers).  n and F must
  * match the stream header.  Values come out in in-block sorted order (see
  * d_perm above).  d_ws: at least gpz_decompress_workspace_bytes (NULL: the
- * library allocates).  Synchronizes `stream` (to report corruption). */
+ * library allocates).  Synchronizes `stream` (to report corruption).  A
+ * float64 stream (GPZ_STREAM_F64) gives GPZ_EINVAL: use gpz_decompress_f64. */
 int gpz_decompress(const void *d_in, uint64_t in_bytes, float *const *h_fields_out, uint64_t n,
                    uint32_t nfields, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* As gpz_decompress for a float64 stream, into F device arrays of n doubles
+ * (fields coded with float32 steps are widened exactly).  A float32 stream
+ * gives GPZ_EINVAL. */
+int gpz_decompress_f64(const void *d_in, uint64_t in_bytes, double *const *h_fields_out,
+                       uint64_t n, uint32_t nfields, void *d_ws, uint64_t ws_bytes, void *stream);
 
 /* As gpz_decompress without any host synchronization (graph-capturable):
  * the caller supplies the parameters the stream was written with (they are
@@ -198,6 +237,7 @@ typedef struct {
     uint64_t n;
     uint32_t nfields, block_size, seg_bits, key_fields;
     uint64_t nblocks;
+    uint32_t flags; /* GPZ_STREAM_F64 | GPZ_STREAM_WIDE */
 } gpz_info;
 int gpz_inspect(const void *h_prefix, uint64_t bytes, gpz_info *out);
 
@@ -292,15 +332,15 @@ int gpz_batch_destroy(gpz_batch *b);
  * an event pair around each of its kernels.  gpz_timing_collect waits for
  * the recorded events, adds up the durations per kernel kind into
  * total_ms[kind] with launch counts[kind] (kind 0 encode, 1 workspace
- * clearing, 2 decode, 3 length scan, 4 record copy; arrays of nkinds
- * entries) and clears the log. */
+ * clearing, 2 decode, 3 length scan, 4 record copy, 5 the generic kernels;
+ * arrays of nkinds entries) and clears the log. */
 int gpz_set_timing(int enable);
 int gpz_timing_collect(double *total_ms, uint32_t *counts, int nkinds);
 
 /* Like gpz_set_timing, for a subset of the kernel kinds: bit k of mask times
- * kind k (0 turns timing off; 0x1F is every kind).  Each timed kernel costs
+ * kind k (0 turns timing off; 0x3F is every kind).  Each timed kernel costs
  * an event pair on its stream, so timing only the kernels of interest keeps
- * the others' launches unchanged.  GPZ_EINVAL for bits beyond kind 4. */
+ * the others' launches unchanged.  GPZ_EINVAL for bits beyond kind 5. */
 int gpz_set_timing_kinds(uint32_t mask);
 
 const char *gpz_strerror(int status);

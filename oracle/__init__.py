@@ -33,7 +33,7 @@ class OracleError(RuntimeError):
 def build_oracle() -> str:
     """Compile the oracle shared library (always recompiles)."""
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.tmp{os.getpid()}"  # concurrent builds never share a file
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            "-o", tmp, SRC, "-lm"]
     subprocess.run(cmd, check=True)
@@ -49,7 +49,7 @@ def build_fuzz_driver() -> str:
     """Compile the stream-reader robustness driver with AddressSanitizer and
     UndefinedBehaviorSanitizer (host code only)."""
     os.makedirs(os.path.dirname(FUZZ_BIN), exist_ok=True)
-    tmp = FUZZ_BIN + ".tmp"
+    tmp = f"{FUZZ_BIN}.tmp{os.getpid()}"  # concurrent builds never share a file
     cmd = ["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=undefined", "-o", tmp, SRC, FUZZ_SRC, "-lm"]
     subprocess.run(cmd, check=True)

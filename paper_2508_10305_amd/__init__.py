@@ -23,7 +23,8 @@ GPZ_OK, GPZ_EINVAL, GPZ_ENOSPC, GPZ_ECORRUPT, GPZ_EDEVICE, GPZ_ENOMEM, GPZ_EUNSU
 EXPORTS = (
     "gpz_default_params", "gpz_max_compressed_bytes", "gpz_compress_workspace_bytes",
     "gpz_decompress_workspace_bytes", "gpz_compress", "gpz_compress_async", "gpz_decompress",
-    "gpz_decompress_async", "gpz_stats_workspace_bytes", "gpz_bound_check", "gpz_error_stats",
+    "gpz_decompress_async", "gpz_compress_f64", "gpz_max_compressed_bytes_f64",
+    "gpz_compress_workspace_bytes_f64", "gpz_decompress_f64", "gpz_stats_workspace_bytes", "gpz_bound_check", "gpz_error_stats",
     "gpz_stream_stats", "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
     "gpz_set_timing", "gpz_set_timing_kinds", "gpz_timing_collect", "gpz_strerror",
     "gpz_default_batch_config",
@@ -70,7 +71,8 @@ class FieldError(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("nfields", ctypes.c_uint32),
                 ("block_size", ctypes.c_uint32), ("seg_bits", ctypes.c_uint32),
-                ("key_fields", ctypes.c_uint32), ("nblocks", ctypes.c_uint64)]
+                ("key_fields", ctypes.c_uint32), ("nblocks", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
 
 
 _LIB = None
@@ -102,6 +104,14 @@ def _lib():
         L.gpz_decompress.restype = ctypes.c_int
         L.gpz_decompress_async.argtypes = [vp, u64, vp, u64, u32, pp, vp, vp]
         L.gpz_decompress_async.restype = ctypes.c_int
+        L.gpz_compress_f64.argtypes = L.gpz_compress.argtypes
+        L.gpz_compress_f64.restype = ctypes.c_int
+        L.gpz_max_compressed_bytes_f64.argtypes = [u64, u32, pp]
+        L.gpz_max_compressed_bytes_f64.restype = u64
+        L.gpz_compress_workspace_bytes_f64.argtypes = [u64, u32, pp]
+        L.gpz_compress_workspace_bytes_f64.restype = u64
+        L.gpz_decompress_f64.argtypes = L.gpz_decompress.argtypes
+        L.gpz_decompress_f64.restype = ctypes.c_int
         L.gpz_stats_workspace_bytes.argtypes = [u32]
         L.gpz_stats_workspace_bytes.restype = u64
         L.gpz_bound_check.argtypes = [vp, vp, vp, u64, u32, vp, vp, vp, vp, u64, vp]
@@ -177,14 +187,15 @@ def _ptr_array(tensors: Sequence) -> ctypes.Array:
     return arr
 
 
-def _check_fields(fields: Sequence, n: Optional[int] = None):
+def _check_fields(fields: Sequence, n: Optional[int] = None, dtype=None):
     torch = _torch()
+    dtype = torch.float32 if dtype is None else dtype
     if len(fields) < 1 or len(fields) > 64:
         raise ValueError("1..64 fields")
     n = fields[0].numel() if n is None else n
     for f in fields:
-        if f.dtype != torch.float32 or not f.is_cuda or not f.is_contiguous() or f.numel() != n:
-            raise ValueError("fields must be contiguous float32 CUDA tensors of equal length")
+        if f.dtype != dtype or not f.is_cuda or not f.is_contiguous() or f.numel() != n:
+            raise ValueError(f"fields must be contiguous {dtype} CUDA tensors of equal length")
     return n
 
 
@@ -300,6 +311,50 @@ def decompress_async(stream_bytes, n: int, nfields: int, out: List, err, p: Opti
     _check(rc, "gpz_decompress_async")
 
 
+def compress_f64(fields: Sequence, eb, *, block_size: int = 1024, seg_bits: int = 3,
+                 key_fields: Optional[int] = None, want_perm: bool = False, stream=None):
+    """Compress SoA float64 CUDA tensors (Sec. 5.1: float32 steps per field and
+    block where they meet the bound, 64-bit steps elsewhere); float32 bounds.
+    Returns (uint8 CUDA tensor, perm or None)."""
+    torch = _torch()
+    F = len(fields)
+    n = _check_fields(fields, dtype=torch.float64)
+    p = params(F, block_size, seg_bits, key_fields)
+    dev = fields[0].device
+    out = torch.empty(int(_lib().gpz_max_compressed_bytes_f64(n, F, ctypes.byref(p))),
+                      dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(int(_lib().gpz_compress_workspace_bytes_f64(n, F, ctypes.byref(p))), 256),
+                     dtype=torch.uint8, device=dev)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if want_perm else None
+    ebs = _eb_array(eb, F)
+    nbytes = ctypes.c_uint64(0)
+    rc = _lib().gpz_compress_f64(
+        ctypes.cast(_ptr_array(fields), ctypes.c_void_p), n, F,
+        ebs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), out.data_ptr(), out.numel(),
+        ctypes.byref(nbytes), perm.data_ptr() if want_perm else None, ws.data_ptr(), ws.numel(),
+        _stream_handle(stream))
+    _check(rc, "gpz_compress_f64")
+    return out[: nbytes.value].clone(), (perm[:n].clone() if want_perm else None)
+
+
+def decompress_f64(stream_bytes, n: int, nfields: int, out: Optional[List] = None, ws=None,
+                   stream=None) -> List:
+    """Decompress a float64 stream (uint8 CUDA tensor) into F float64 tensors."""
+    torch = _torch()
+    if not stream_bytes.is_cuda or stream_bytes.dtype != torch.uint8:
+        raise ValueError("stream must be a uint8 CUDA tensor")
+    if out is None:
+        out = [torch.empty(max(n, 1), dtype=torch.float64, device=stream_bytes.device)[:n]
+               for _ in range(nfields)]
+    if ws is None:
+        ws = torch.empty(256, dtype=torch.uint8, device=stream_bytes.device)
+    rc = _lib().gpz_decompress_f64(stream_bytes.data_ptr(), stream_bytes.numel(),
+                                   ctypes.cast(_ptr_array(out), ctypes.c_void_p), n, nfields,
+                                   ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    _check(rc, "gpz_decompress_f64")
+    return out
+
+
 def stats_workspace(nfields: int, device="cuda"):
     """A device workspace for the reporting calls (bound check, error and
     stream statistics, field range) of up to `nfields` fields."""
@@ -398,10 +453,11 @@ def inspect(prefix: bytes) -> dict:
     buf = ctypes.create_string_buffer(bytes(prefix), len(prefix))
     _check(_lib().gpz_inspect(buf, len(prefix), ctypes.byref(info)), "gpz_inspect")
     return dict(n=info.n, nfields=info.nfields, block_size=info.block_size,
-                seg_bits=info.seg_bits, key_fields=info.key_fields, nblocks=info.nblocks)
+                seg_bits=info.seg_bits, key_fields=info.key_fields, nblocks=info.nblocks,
+                flags=info.flags)
 
 
-KERNEL_KINDS = ("encode", "prepare", "decode", "scan", "copy")
+KERNEL_KINDS = ("encode", "prepare", "decode", "scan", "copy", "generic")
 
 
 def set_timing(enable: bool, kinds: Optional[Sequence[str]] = None):

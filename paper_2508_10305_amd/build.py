@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libgpz.so")
-SOURCES = ["api.hip", "encode.hip", "decode.hip", "aux.hip", "batch.hip"]
+SOURCES = ["api.hip", "encode.hip", "decode.hip", "aux.hip", "batch.hip", "generic.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -14,7 +14,7 @@ namespace {
 
 // Optional kernel timing: HIP events recorded around each kernel on the
 // launch stream, collected later by gpz_timing_collect.
-enum { kEncode = 0, kPrepare = 1, kDecode = 2, kScan = 3, kCopy = 4, kKinds = 5 };
+enum { kEncode = 0, kPrepare = 1, kDecode = 2, kScan = 3, kCopy = 4, kGeneric = 5, kKinds = 6 };
 struct TimedLaunch {
     int kind;
     hipEvent_t a, b;
@@ -56,6 +56,7 @@ bool params_ok(uint32_t F, const gpz_params& p) {
     return true;
 }
 
+// Block sizes of the wave-per-block kernels; the generic ones take any.
 bool kernel_block_size(uint32_t B) { return B == 256 || B == 512 || B == 1024 || B == 2048; }
 
 gpz_params resolve(const gpz_params* p, uint32_t F) {
@@ -72,33 +73,44 @@ struct CompressWs {
     uint64_t* state;    // look-back word per block
     uint32_t* ticket;   // block ticket counter (right after the look-back words)
     uint64_t* total;    // stream size
+    uint32_t* defer_count;  // blocks left to the generic encoder
+    uint32_t* wide_flag;    // a record codes a field with 64-bit steps
+    uint32_t* done;         // workgroups of the deferred-block walk that have finished
     uint64_t clear_words;  // 32-bit words from `state` to clear before a launch
     // three-step compaction
     uint32_t* lens;
     uint32_t* supsum;
     uint64_t* supoff;
+    uint32_t* defer;    // the deferred block list
     uint32_t slot_words;
     uint64_t bytes;
 };
 
-CompressWs layout(uint64_t n, uint32_t F, uint32_t B, char* base) {
+// vw: words per value (1 float32, 2 float64)
+CompressWs layout(uint64_t n, uint32_t F, uint32_t B, uint32_t vw, char* base) {
     CompressWs w{};
     const uint64_t nb = nblocks_of(n, B), ns = nsuper_of(nb);
-    w.slot_words = (uint32_t)((1 + (uint64_t)F * B + 3) & ~uint64_t(3));
+    w.slot_words = (uint32_t)((1 + (uint64_t)F * B * vw + 3) & ~uint64_t(3));
     uint64_t o = 0;
     w.temp = reinterpret_cast<uint32_t*>(base + o);
     o = align256(o + nb * w.slot_words * 4ull);
-    // look-back words, ticket, total and the superblock sums are contiguous:
-    // one fill clears what either compaction needs zeroed
+    // look-back words, ticket, total, deferred-block count, wide flag and the
+    // superblock sums are contiguous: one fill clears what either compaction
+    // needs zeroed
     w.state = reinterpret_cast<uint64_t*>(base + o);
     w.ticket = reinterpret_cast<uint32_t*>(base + o + nb * 8);
     w.total = reinterpret_cast<uint64_t*>(base + o + nb * 8 + 8);
-    w.supsum = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 16);
-    w.clear_words = 2 * nb + 4 + ns;
-    o = align256(o + nb * 8 + 16 + ns * 4);
+    w.defer_count = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 16);
+    w.wide_flag = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 20);
+    w.done = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 24);
+    w.supsum = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 28);
+    w.clear_words = 2 * nb + 7 + ns;
+    o = align256(o + nb * 8 + 28 + ns * 4);
     w.supoff = reinterpret_cast<uint64_t*>(base + o);
     o = align256(o + ns * 8);
     w.lens = reinterpret_cast<uint32_t*>(base + o);
+    o = align256(o + nb * 4);
+    w.defer = reinterpret_cast<uint32_t*>(base + o);
     o = align256(o + nb * 4);
     w.bytes = o;
     return w;
@@ -107,26 +119,35 @@ CompressWs layout(uint64_t n, uint32_t F, uint32_t B, char* base) {
 int to_status(hipError_t e) { return e == hipSuccess ? GPZ_OK : GPZ_EDEVICE; }
 bool alloc_fault();
 
-// Shared body of gpz_compress / gpz_compress_async.
-int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const float* h_eb,
+// Shared body of the compress entry points (float32 or float64 fields).
+// The wave-per-block encoder takes float32 snapshots at block sizes
+// 256..2048 and leaves blocks that need 64-bit grid steps to the generic
+// encoder; float64 fields and other block sizes go to the generic encoder
+// whole.
+int compress_impl(const void* const* h_fields, bool f64, uint64_t n, uint32_t F, const float* h_eb,
                   const gpz_params* pp, void* d_out, uint64_t cap, uint64_t* h_out_bytes,
                   uint64_t* d_out_bytes, uint32_t* d_perm, void* d_ws, uint64_t ws_bytes,
                   hipStream_t s, bool sync) {
     if (F < 1 || F > kMaxFields || !h_eb) return GPZ_EINVAL;
     gpz_params p = resolve(pp, F);
     if (!params_ok(F, p)) return GPZ_EINVAL;
-    if (!kernel_block_size(p.block_size)) return GPZ_EUNSUPPORTED;
+    const bool single = (p.flags & GPZ_FLAG_SINGLE_PASS) != 0;
+    const bool generic = f64 || !kernel_block_size(p.block_size);
+    // the single pass exists for the wave-per-block encoder only
+    if (single && generic) return GPZ_EUNSUPPORTED;
     if (n > 0 && !h_fields) return GPZ_EINVAL;
     if (!d_out) return GPZ_EINVAL;
-    // one 64-lane workgroup per block: the dispatch size (64 * blocks) must fit 32 bits
-    if (nblocks_of(n, p.block_size) > ((uint64_t)1 << 26)) return GPZ_EINVAL;
+    // one workgroup per block: the dispatch size (64 or 256 lanes per block)
+    // must fit 32 bits
+    if (nblocks_of(n, p.block_size) > ((uint64_t)1 << (generic ? 24 : 26))) return GPZ_EINVAL;
     for (uint32_t f = 0; f < F; f++) {
         if (!eb_valid(h_eb[f])) return GPZ_EINVAL;
         if (n > 0 && !h_fields[f]) return GPZ_EINVAL;
     }
     const uint32_t B = p.block_size;
+    const uint32_t vw = f64 ? 2u : 1u;
     const uint64_t nb = nblocks_of(n, B);
-    CompressWs probe = layout(n, F, B, nullptr);
+    CompressWs probe = layout(n, F, B, vw, nullptr);
     char* ws = static_cast<char*>(d_ws);
     bool owned = false;
     if (!ws) {
@@ -136,11 +157,11 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     } else if (ws_bytes < probe.bytes) {
         return GPZ_EINVAL;
     }
-    CompressWs w = layout(n, F, B, ws);
+    CompressWs w = layout(n, F, B, vw, ws);
 
     EncodeArgs ea{};
     for (uint32_t f = 0; f < F; f++) {
-        ea.x[f] = n ? h_fields[f] : nullptr;
+        ea.x[f] = n ? static_cast<const float*>(h_fields[f]) : nullptr;
         ea.eb[f] = h_eb[f];
         ea.twoeb[f] = 2.0f * h_eb[f];
         ea.inv[f] = 1.0f / ea.twoeb[f];
@@ -161,9 +182,12 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
     ea.prefix = prefix_words(n, F, B);
     ea.total_bytes = w.total;
     ea.ext_bytes = d_out_bytes;
-    const bool single = (p.flags & GPZ_FLAG_SINGLE_PASS) != 0;
     ea.lens = w.lens;
     ea.supsum = w.supsum;
+    ea.f64 = f64 ? 1u : 0u;
+    ea.defer = w.defer;
+    ea.defer_count = w.defer_count;
+    ea.wide_flag = w.wide_flag;
 
     Timer tm(s);
     tm.begin(kPrepare);
@@ -171,7 +195,8 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
         launch_fill_u32(reinterpret_cast<uint32_t*>(w.state), 0u, w.clear_words, s));
     tm.end();
     tm.begin(kEncode);
-    if (rc == GPZ_OK) rc = to_status(launch_encode(ea, single, s));
+    if (rc == GPZ_OK) rc = to_status(generic ? launch_encode_generic(ea, false, s)
+                                             : launch_encode(ea, single, s));
     tm.end();
     if (!single) {
         ScanArgs sa{};
@@ -191,6 +216,8 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
         sa.K = p.seg_bits;
         sa.KF = p.key_fields;
         sa.nblocks = (uint32_t)nb;
+        sa.f64 = ea.f64;
+        sa.wide_flag = w.wide_flag;
         ca.temp = w.temp;
         ca.lens = w.lens;
         ca.supoff = w.supoff;
@@ -200,8 +227,12 @@ int compress_impl(const float* const* h_fields, uint64_t n, uint32_t F, const fl
         ca.slot_words = w.slot_words;
         ca.nblocks = (uint32_t)nb;
         ca.F = F;
+        // after the wave-per-block encoder, the walk over the blocks it left
+        // for 64-bit steps and the scan share one launch
         tm.begin(kScan);
-        if (rc == GPZ_OK) rc = to_status(launch_scan(sa, s));
+        if (rc == GPZ_OK)
+            rc = to_status(generic ? launch_scan(sa, s)
+                                   : launch_encode_deferred_then_scan(ea, sa, w.done, s));
         tm.end();
         tm.begin(kCopy);
         if (rc == GPZ_OK) rc = to_status(launch_copy(ca, s));
@@ -299,17 +330,31 @@ void gpz_default_params(gpz_params* p, uint32_t nfields) {
     p->flags = 0;
 }
 
-uint64_t gpz_max_compressed_bytes(uint64_t n, uint32_t nfields, const gpz_params* pp) {
+static uint64_t max_bytes(uint64_t n, uint32_t nfields, const gpz_params* pp, uint32_t vw) {
     gpz_params p = resolve(pp, nfields);
     if (!params_ok(nfields, p)) return 0;
     uint64_t nb = nblocks_of(n, p.block_size);
-    return 4 * (prefix_words(n, nfields, p.block_size) + nb + (uint64_t)nfields * n);
+    return 4 * (prefix_words(n, nfields, p.block_size) + nb + (uint64_t)nfields * n * vw);
+}
+
+uint64_t gpz_max_compressed_bytes(uint64_t n, uint32_t nfields, const gpz_params* pp) {
+    return max_bytes(n, nfields, pp, 1);
+}
+
+uint64_t gpz_max_compressed_bytes_f64(uint64_t n, uint32_t nfields, const gpz_params* pp) {
+    return max_bytes(n, nfields, pp, 2);
 }
 
 uint64_t gpz_compress_workspace_bytes(uint64_t n, uint32_t nfields, const gpz_params* pp) {
     gpz_params p = resolve(pp, nfields);
     if (!params_ok(nfields, p)) return 0;
-    return layout(n, nfields, p.block_size, nullptr).bytes;
+    return layout(n, nfields, p.block_size, 1, nullptr).bytes;
+}
+
+uint64_t gpz_compress_workspace_bytes_f64(uint64_t n, uint32_t nfields, const gpz_params* pp) {
+    gpz_params p = resolve(pp, nfields);
+    if (!params_ok(nfields, p)) return 0;
+    return layout(n, nfields, p.block_size, 2, nullptr).bytes;
 }
 
 uint64_t gpz_decompress_workspace_bytes(void) { return 256; }
@@ -317,8 +362,18 @@ uint64_t gpz_decompress_workspace_bytes(void) { return 256; }
 int gpz_compress(const float* const* h_fields, uint64_t n, uint32_t nfields, const float* h_eb,
                  const gpz_params* p, void* d_out, uint64_t out_capacity, uint64_t* h_out_bytes,
                  uint32_t* d_perm, void* d_ws, uint64_t ws_bytes, void* stream) {
-    return compress_impl(h_fields, n, nfields, h_eb, p, d_out, out_capacity, h_out_bytes, nullptr,
-                         d_perm, d_ws, ws_bytes, static_cast<hipStream_t>(stream), true);
+    return compress_impl(reinterpret_cast<const void* const*>(h_fields), false, n, nfields, h_eb, p,
+                         d_out, out_capacity, h_out_bytes, nullptr, d_perm, d_ws, ws_bytes,
+                         static_cast<hipStream_t>(stream), true);
+}
+
+int gpz_compress_f64(const double* const* h_fields, uint64_t n, uint32_t nfields,
+                     const float* h_eb, const gpz_params* p, void* d_out, uint64_t out_capacity,
+                     uint64_t* h_out_bytes, uint32_t* d_perm, void* d_ws, uint64_t ws_bytes,
+                     void* stream) {
+    return compress_impl(reinterpret_cast<const void* const*>(h_fields), true, n, nfields, h_eb, p,
+                         d_out, out_capacity, h_out_bytes, nullptr, d_perm, d_ws, ws_bytes,
+                         static_cast<hipStream_t>(stream), true);
 }
 
 int gpz_compress_async(const float* const* h_fields, uint64_t n, uint32_t nfields,
@@ -328,24 +383,30 @@ int gpz_compress_async(const float* const* h_fields, uint64_t n, uint32_t nfield
     if (!d_out_bytes || !d_ws) return GPZ_EINVAL;
     uint64_t need = gpz_max_compressed_bytes(n, nfields, p);
     if (need == 0 || out_capacity < need) return GPZ_EINVAL;
-    return compress_impl(h_fields, n, nfields, h_eb, p, d_out, out_capacity, nullptr, d_out_bytes,
-                         d_perm, d_ws, ws_bytes, static_cast<hipStream_t>(stream), false);
+    return compress_impl(reinterpret_cast<const void* const*>(h_fields), false, n, nfields, h_eb, p,
+                         d_out, out_capacity, nullptr, d_out_bytes, d_perm, d_ws, ws_bytes,
+                         static_cast<hipStream_t>(stream), false);
 }
 
-static int decompress_impl(const void* d_in, uint64_t in_bytes, float* const* h_out, uint64_t n,
-                           uint32_t F, const gpz_params& p, uint32_t* d_err, hipStream_t s,
-                           bool exact) {
+// Shared body of the decompress entry points.  The wave-per-block decoder
+// takes float32 streams at block sizes 256..2048 (it decodes a record with a
+// wide field itself, with the generic record decoder); float64 streams and
+// other block sizes go to the generic decoder.
+static int decompress_impl(const void* d_in, uint64_t in_bytes, void* const* h_out, bool f64,
+                           uint64_t n, uint32_t F, const gpz_params& p, uint32_t* d_err,
+                           hipStream_t s, bool exact) {
     const uint32_t B = p.block_size;
     const uint64_t nb = nblocks_of(n, B);
     const uint64_t pre = prefix_words(n, F, B);
-    if (nb > ((uint64_t)1 << 26)) return GPZ_EINVAL;
+    const bool generic = f64 || !kernel_block_size(B);
+    if (nb > ((uint64_t)1 << (generic ? 24 : 26))) return GPZ_EINVAL;
     if (in_bytes < 4 * pre || (exact && in_bytes % 4 != 0)) return GPZ_ECORRUPT;
     // (no blocks: the decode launch checks the header and eb table on the
     // device, so this path never waits for the stream either)
     DecodeArgs da{};
     da.in = static_cast<const uint32_t*>(d_in);
     da.in_words = in_bytes / 4;
-    for (uint32_t f = 0; f < F; f++) da.y[f] = n ? h_out[f] : nullptr;
+    for (uint32_t f = 0; f < F; f++) da.y[f] = n ? static_cast<float*>(h_out[f]) : nullptr;
     da.n = n;
     da.F = F;
     da.K = p.seg_bits;
@@ -355,31 +416,45 @@ static int decompress_impl(const void* d_in, uint64_t in_bytes, float* const* h_
     da.prefix = pre;
     da.err = d_err;
     da.exact = exact ? 1u : 0u;
+    da.f64 = f64 ? 1u : 0u;
     int rc = to_status(launch_fill_u32(d_err, 0u, 1, s));
     Timer tm(s);
+    if (generic && nb > 0) {
+        tm.begin(kGeneric);
+        if (rc == GPZ_OK) rc = to_status(launch_decode_generic(da, s));
+        tm.end();
+        return rc;
+    }
     tm.begin(kDecode);
     if (rc == GPZ_OK) rc = to_status(launch_decode(da, s));
     tm.end();
     return rc;
 }
 
-int gpz_decompress(const void* d_in, uint64_t in_bytes, float* const* h_fields_out, uint64_t n,
-                   uint32_t nfields, void* d_ws, uint64_t ws_bytes, void* stream) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!d_in || nfields < 1 || nfields > kMaxFields) return GPZ_EINVAL;
-    if (n > 0 && !h_fields_out) return GPZ_EINVAL;
-    for (uint32_t f = 0; n > 0 && f < nfields; f++)
-        if (!h_fields_out[f]) return GPZ_EINVAL;
+// Host copy of a stream's header: its parameters and flags (synchronizes).
+static int read_header(const void* d_in, uint64_t in_bytes, hipStream_t s, gpz_info* info) {
     if (in_bytes < 4 * kHeaderWords) return GPZ_ECORRUPT;
     uint32_t hdr[kHeaderWords];
     if (hipMemcpyAsync(hdr, d_in, sizeof(hdr), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return GPZ_EDEVICE;
+    return gpz_inspect(hdr, sizeof(hdr), info);
+}
+
+// Synchronous decompression of either value type.
+static int decompress_sync(const void* d_in, uint64_t in_bytes, void* const* h_fields_out,
+                           bool f64, uint64_t n, uint32_t nfields, void* d_ws, uint64_t ws_bytes,
+                           hipStream_t s) {
+    if (!d_in || nfields < 1 || nfields > kMaxFields) return GPZ_EINVAL;
+    if (n > 0 && !h_fields_out) return GPZ_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < nfields; f++)
+        if (!h_fields_out[f]) return GPZ_EINVAL;
     gpz_info info;
-    int rc = gpz_inspect(hdr, sizeof(hdr), &info);
+    int rc = read_header(d_in, in_bytes, s, &info);
     if (rc) return rc;
     if (info.n != n || info.nfields != nfields) return GPZ_EINVAL;
-    if (!kernel_block_size(info.block_size)) return GPZ_EUNSUPPORTED;
+    // the caller's value type must be the stream's
+    if (((info.flags & GPZ_STREAM_F64) != 0) != f64) return GPZ_EINVAL;
     gpz_params p{info.block_size, info.seg_bits, info.key_fields, 0};
     uint32_t* err = static_cast<uint32_t*>(d_ws);
     bool owned = false;
@@ -389,7 +464,7 @@ int gpz_decompress(const void* d_in, uint64_t in_bytes, float* const* h_fields_o
     } else if (ws_bytes < gpz_decompress_workspace_bytes()) {
         return GPZ_EINVAL;
     }
-    rc = decompress_impl(d_in, in_bytes, h_fields_out, n, nfields, p, err, s, true);
+    rc = decompress_impl(d_in, in_bytes, h_fields_out, f64, n, nfields, p, err, s, true);
     uint32_t e = 0;
     if (rc == GPZ_OK) rc = to_status(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s));
     if (rc == GPZ_OK) rc = to_status(hipStreamSynchronize(s));
@@ -401,16 +476,30 @@ int gpz_decompress(const void* d_in, uint64_t in_bytes, float* const* h_fields_o
     return rc;
 }
 
+int gpz_decompress(const void* d_in, uint64_t in_bytes, float* const* h_fields_out, uint64_t n,
+                   uint32_t nfields, void* d_ws, uint64_t ws_bytes, void* stream) {
+    return decompress_sync(d_in, in_bytes, reinterpret_cast<void* const*>(h_fields_out), false, n,
+                           nfields, d_ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int gpz_decompress_f64(const void* d_in, uint64_t in_bytes, double* const* h_fields_out,
+                       uint64_t n, uint32_t nfields, void* d_ws, uint64_t ws_bytes,
+                       void* stream) {
+    return decompress_sync(d_in, in_bytes, reinterpret_cast<void* const*>(h_fields_out), true, n,
+                           nfields, d_ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
 int gpz_decompress_async(const void* d_in, uint64_t in_bytes, float* const* h_fields_out,
                          uint64_t n, uint32_t nfields, const gpz_params* pp, uint32_t* d_error,
                          void* stream) {
     if (!d_in || !d_error || nfields < 1 || nfields > kMaxFields) return GPZ_EINVAL;
     if (n > 0 && !h_fields_out) return GPZ_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < nfields; f++)
+        if (!h_fields_out[f]) return GPZ_EINVAL;
     gpz_params p = resolve(pp, nfields);
     if (!params_ok(nfields, p)) return GPZ_EINVAL;
-    if (!kernel_block_size(p.block_size)) return GPZ_EUNSUPPORTED;
-    return decompress_impl(d_in, in_bytes, h_fields_out, n, nfields, p, d_error,
-                           static_cast<hipStream_t>(stream), false);
+    return decompress_impl(d_in, in_bytes, reinterpret_cast<void* const*>(h_fields_out), false, n,
+                           nfields, p, d_error, static_cast<hipStream_t>(stream), false);
 }
 
 uint64_t gpz_stats_workspace_bytes(uint32_t nfields) {
@@ -574,7 +663,10 @@ int gpz_inspect(const void* h_prefix, uint64_t bytes, gpz_info* out) {
     if (bytes < 4 * kHeaderWords) return GPZ_ECORRUPT;
     uint32_t w[kHeaderWords];
     memcpy(w, h_prefix, sizeof(w));
-    if (w[0] != kMagic || w[1] != kVersion) return GPZ_ECORRUPT;
+    const uint32_t flags = w[1] >> 16;
+    if (w[0] != kMagic || (w[1] & 0xFFFFu) != kVersion ||
+        (flags & ~(uint32_t)(GPZ_STREAM_F64 | GPZ_STREAM_WIDE)) != 0)
+        return GPZ_ECORRUPT;
     gpz_params p{w[5], w[6] & 0xFFu, (w[6] >> 8) & 0xFFu, 0};
     if ((w[6] >> 16) != 0 || !params_ok(w[4], p)) return GPZ_ECORRUPT;
     uint64_t n = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
@@ -586,6 +678,7 @@ int gpz_inspect(const void* h_prefix, uint64_t bytes, gpz_info* out) {
     out->seg_bits = p.seg_bits;
     out->key_fields = p.key_fields;
     out->nblocks = nb;
+    out->flags = flags;
     return GPZ_OK;
 }
 
@@ -631,7 +724,7 @@ const char* gpz_strerror(int status) {
         case GPZ_ECORRUPT: return "corrupt or inconsistent stream";
         case GPZ_EDEVICE: return "HIP runtime error";
         case GPZ_ENOMEM: return "workspace allocation failed";
-        case GPZ_EUNSUPPORTED: return "block size without a gfx950 kernel";
+        case GPZ_EUNSUPPORTED: return "request without a gfx950 kernel (single pass with float64 or a block size outside 256..2048)";
         default: return "unknown status";
     }
 }

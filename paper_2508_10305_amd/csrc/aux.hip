@@ -3,6 +3,8 @@
 // offset together with the stream header and tables.  Also: a fill kernel
 // (used instead of hipMemset so the sequence stays graph-capturable), the
 // error-bound check and the per-field range reduction.
+#include <atomic>
+
 #include "gpz_internal.h"
 
 namespace gpz {
@@ -10,56 +12,9 @@ namespace {
 
 constexpr uint32_t kScanThreads = 1024;
 
-// Exclusive scan of the per-superblock record sizes (one workgroup; there
-// are only ceil(nblocks / 64) of them): thread t sums a contiguous chunk, the
-// chunk totals are scanned in LDS, then each thread writes its offsets.  The
-// last thread publishes the stream size; when the stream fits the output
-// buffer the workgroup also writes the header and the eb table.
-__device__ __forceinline__ void scan_body(const ScanArgs& a, uint64_t* part) {
-    const uint32_t t = threadIdx.x;
-    const uint32_t ns = a.nsuper;
-    const uint32_t chunk = (ns + kScanThreads - 1) / kScanThreads;
-    const uint32_t lo = t * chunk;
-    const uint32_t hi = lo + chunk < ns ? lo + chunk : ns;
-    uint64_t sum = 0;
-    for (uint32_t i = lo; i < hi; i++) sum += a.supsum[i];
-    part[t] = sum;
-    __syncthreads();
-    for (uint32_t o = 1; o < kScanThreads; o <<= 1) {
-        uint64_t v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint64_t run = part[t] - sum;
-    for (uint32_t i = lo; i < hi; i++) {
-        a.supoff[i] = run;
-        run += a.supsum[i];
-    }
-    const uint64_t bytes = 4 * (a.prefix + part[kScanThreads - 1]);
-    if (t == kScanThreads - 1) {
-        *a.total_bytes = bytes;
-        if (a.ext_bytes) *a.ext_bytes = bytes;
-    }
-    if (bytes <= a.capacity) {
-        if (t == 0) {
-            a.out[0] = kMagic;
-            a.out[1] = kVersion;
-            a.out[2] = (uint32_t)(a.n & 0xFFFFFFFFu);
-            a.out[3] = (uint32_t)(a.n >> 32);
-            a.out[4] = a.F;
-            a.out[5] = a.B;
-            a.out[6] = a.K | (a.KF << 8);
-            a.out[7] = a.nblocks;
-        }
-        uint32_t* ebt = a.out + kHeaderWords + 2 * nsuper_of(a.nblocks);
-        for (uint32_t f = t; f < a.F; f += kScanThreads) ebt[f] = a.eb_bits[f];
-    }
-}
-
 __global__ __launch_bounds__(kScanThreads) void scan_lengths(ScanArgs a) {
     __shared__ uint64_t part[kScanThreads];
-    scan_body(a, part);
+    scan_superblocks<kScanThreads>(a, part);
 }
 
 __global__ __launch_bounds__(kScanThreads) void scan_lengths_batch(const ScanArgs* jobs,
@@ -67,7 +22,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_lengths_batch(const ScanArg
     __shared__ uint64_t part[kScanThreads];
     const uint32_t njobs = L->njobs;
     for (uint32_t j = blockIdx.x; j < njobs; j += gridDim.x) {
-        scan_body(jobs[j], part);
+        scan_superblocks<kScanThreads>(jobs[j], part);
         __syncthreads();
     }
 }
@@ -286,6 +241,7 @@ __global__ __launch_bounds__(256) void stream_stats_kernel(StatsArgs a) {
     const uint32_t* sup = a.in + kHeaderWords;
     const uint32_t* lt = sup + 2 * nsup + a.F;
     const uint64_t rec_total = a.in_words - a.prefix;
+    const uint32_t vw = (a.in[1] >> 16) & 1u ? 2u : 1u;  // words per value (float64 stream: 2)
     bool bad = false, raw = false;
     uint64_t off = 0, pos = 0;
     uint32_t len = 0, nn = 0;
@@ -305,11 +261,11 @@ __global__ __launch_bounds__(256) void stream_stats_kernel(StatsArgs a) {
             rec += off;
             raw = (rec[0] & 3u) == 1u;
             if (raw) {
-                bad = len != 1 + a.F * nn;
+                bad = len != 1 + a.F * nn * vw;
             } else {
                 bad = len < 2;
                 if (!bad) {
-                    const uint32_t U = rec[0] >> 2, h1 = rec[1];
+                    const uint32_t U = (rec[0] & 0x7FFFFFFFu) >> 2, h1 = rec[1];
                     pos = 2 + (uint64_t)words_for(U, h1 & 31u) + words_for(U, (h1 >> 5) & 31u);
                 }
             }
@@ -319,12 +275,15 @@ __global__ __launch_bounds__(256) void stream_stats_kernel(StatsArgs a) {
     for (uint32_t f = 0; f < a.F; f++) {
         uint32_t nout = 0;
         if (walk && !bad) {
-            if (pos + 2 > len) {
+            if (pos + vw + 1 > len) {
                 bad = true;
             } else {
-                const uint32_t wn = rec[pos + 1];
-                nout = wn >> 5;
-                pos += 2 + (uint64_t)words_for(nn, wn & 31u) + 2 * (uint64_t)nout;
+                // field word: w | nout << 5, or w | nout << 6 | 1 << 31 (wide)
+                const uint32_t wn = rec[pos + vw];
+                const bool wide = (wn >> 31) != 0;
+                const uint32_t w = wide ? (wn & 63u) : (wn & 31u);
+                nout = wide ? ((wn >> 6) & 0x1FFFFFFu) : ((wn >> 5) & 0x3FFFFFFu);
+                pos += vw + 1 + (uint64_t)words_for(nn, w) + (uint64_t)(1 + vw) * nout;
             }
         }
         const uint32_t tot = wave_sum_u32(nout);
@@ -340,7 +299,8 @@ struct RangeArgs {
     const float* x[kMaxFields];
     uint64_t n;
     uint32_t F;
-    int* keys;  // order-preserving integer keys: [0, F) minima, [F, 2F) maxima
+    uint64_t cpf;  // chunks per field: ceil((n / 4) / (U * 256))
+    int* keys;     // order-preserving integer keys: [0, F) minima, [F, 2F) maxima
 };
 
 // Order-preserving map of float bits to signed integers (-0 < +0).
@@ -357,53 +317,26 @@ __device__ __forceinline__ void range_take(float v, int& mn, int& mx) {
     }
 }
 
-// Field range over finite values, field = blockIdx.y: grid-stride over
-// 16-byte vectors, four of them in flight per lane; the unaligned head and
-// the tail are done element by element by workgroup 0.
-__global__ __launch_bounds__(256) void field_range_kernel(RangeArgs a) {
-    __shared__ int smin[4], smax[4];
-    const uint32_t f = blockIdx.y;
-    const float* x = a.x[f];
-    int mn = 0x7FFFFFFF, mx = (int)0x80000000;
-    // elements before the first 16-byte boundary
-    const uint64_t head = ((16u - (reinterpret_cast<uintptr_t>(x) & 15u)) & 15u) / 4u;
-    const uint64_t h = head < a.n ? head : a.n;
-    const uint64_t nv = (a.n - h) / 4;  // whole vectors
-    const f32x4* xv = reinterpret_cast<const f32x4*>(x + h);
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    for (; i + 3 * stride < nv; i += 4 * stride) {
-        f32x4 v[4];
-#pragma unroll
-        for (int k = 0; k < 4; k++) v[k] = __builtin_nontemporal_load(xv + i + k * stride);
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            range_take(v[k].x, mn, mx);
-            range_take(v[k].y, mn, mx);
-            range_take(v[k].z, mn, mx);
-            range_take(v[k].w, mn, mx);
-        }
-    }
-    for (; i < nv; i += stride) {
-        const f32x4 v = __builtin_nontemporal_load(xv + i);
-        range_take(v.x, mn, mx);
-        range_take(v.y, mn, mx);
-        range_take(v.z, mn, mx);
-        range_take(v.w, mn, mx);
-    }
-    if (blockIdx.x == 0) {
-        for (uint64_t j = threadIdx.x; j < h; j += 256) range_take(x[j], mn, mx);
-        for (uint64_t j = h + 4 * nv + threadIdx.x; j < a.n; j += 256) range_take(x[j], mn, mx);
-    }
+__device__ __forceinline__ void range_take4(const f32x4& v, int& mn, int& mx) {
+    range_take(v.x, mn, mx);
+    range_take(v.y, mn, mx);
+    range_take(v.z, mn, mx);
+    range_take(v.w, mn, mx);
+}
+
+// Workgroup minimum / maximum of the keys, then one atomic pair per
+// workgroup (atomics of many waves on the same few words serialize).  Every
+// lane calls it (a change of field is workgroup-uniform).
+__device__ __forceinline__ void range_flush(const RangeArgs& a, uint32_t f, int mn, int mx,
+                                            int* smin, int* smax) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         mn = min(mn, __shfl_xor(mn, o));
         mx = max(mx, __shfl_xor(mx, o));
     }
-    const uint32_t w = threadIdx.x >> 6;
     if ((threadIdx.x & 63u) == 0) {
-        smin[w] = mn;
-        smax[w] = mx;
+        smin[threadIdx.x >> 6] = mn;
+        smax[threadIdx.x >> 6] = mx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -411,8 +344,110 @@ __global__ __launch_bounds__(256) void field_range_kernel(RangeArgs a) {
             mn = min(mn, smin[k]);
             mx = max(mx, smax[k]);
         }
-        atomicMin(&a.keys[f], mn);
-        atomicMax(&a.keys[a.F + f], mx);
+        if (mn != 0x7FFFFFFF) atomicMin(&a.keys[f], mn);
+        if (mx != (int)0x80000000) atomicMax(&a.keys[a.F + f], mx);
+    }
+    __syncthreads();
+}
+
+// Chunk c of the flattened (field, chunk) space: its field, the 16-byte
+// vectors of that field past its unaligned head, and the chunk's first vector.
+struct RangeChunk {
+    uint32_t f;
+    const f32x4* xv;
+    uint64_t nv, v0;
+};
+
+__device__ __forceinline__ RangeChunk range_chunk(const RangeArgs& a, uint64_t c, uint64_t chunk) {
+    RangeChunk r;
+    r.f = (uint32_t)(c / a.cpf);
+    const float* x = a.x[r.f];
+    const uint64_t head = ((16u - (reinterpret_cast<uintptr_t>(x) & 15u)) & 15u) / 4u;
+    const uint64_t h = head < a.n ? head : a.n;
+    r.nv = (a.n - h) / 4;
+    r.xv = reinterpret_cast<const f32x4*>(x + h);
+    r.v0 = (c - (uint64_t)r.f * a.cpf) * chunk;
+    return r;
+}
+
+template <int U>
+__device__ __forceinline__ void range_load(const RangeChunk& r, uint64_t chunk, f32x4 (&v)[U]) {
+    const uint64_t i0 = r.v0 + threadIdx.x;
+    if (r.v0 + chunk <= r.nv) {
+#pragma unroll
+        for (int k = 0; k < U; k++) v[k] = __builtin_nontemporal_load(r.xv + i0 + 256 * k);
+    } else {
+        const f32x4 nan4 = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""),
+                            __builtin_nanf("")};
+#pragma unroll
+        for (int k = 0; k < U; k++)
+            v[k] = i0 + 256 * k < r.nv ? __builtin_nontemporal_load(r.xv + i0 + 256 * k) : nan4;
+    }
+}
+
+// Field range over finite values.  The 16-byte vectors of every field are cut
+// into chunks of U * 256 vectors (chunk c belongs to field c / cpf);
+// workgroup g takes chunks g, g + gridDim.x, ...  The loads of the next chunk
+// are issued before the current one is reduced (two register buffers), so
+// the memory stays busy while a wave computes.  Positions past a field's
+// last whole vector load as NaN, which the finite test skips.  Every wave
+// follows the same chunk sequence, so a change of field is
+// workgroup-uniform: the running extrema are then folded into the field's
+// keys.  The elements before a field's first 16-byte boundary and after its
+// last whole vector (at most 3 + 3) are taken by workgroup 0, each lane
+// with its own atomics.
+template <int U>
+__global__ __launch_bounds__(256) void field_range_kernel(RangeArgs a) {
+    __shared__ int smin[4], smax[4];
+    const uint64_t chunk = (uint64_t)U * 256;
+    const uint64_t total = a.cpf * a.F;
+    int mn = 0x7FFFFFFF, mx = (int)0x80000000;
+    uint64_t c = blockIdx.x;
+    if (c < total) {
+        uint32_t cur = 0xFFFFFFFFu;
+        RangeChunk r = range_chunk(a, c, chunk);
+        f32x4 v[U];
+        range_load<U>(r, chunk, v);
+        for (;;) {
+            const uint64_t cn = c + gridDim.x;
+            RangeChunk rn = r;
+            f32x4 w[U];
+            if (cn < total) {
+                rn = range_chunk(a, cn, chunk);
+                range_load<U>(rn, chunk, w);
+            }
+            if (r.f != cur) {
+                if (cur != 0xFFFFFFFFu) range_flush(a, cur, mn, mx, smin, smax);
+                mn = 0x7FFFFFFF;
+                mx = (int)0x80000000;
+                cur = r.f;
+            }
+#pragma unroll
+            for (int k = 0; k < U; k++) range_take4(v[k], mn, mx);
+            if (cn >= total) break;
+            c = cn;
+            r = rn;
+#pragma unroll
+            for (int k = 0; k < U; k++) v[k] = w[k];
+        }
+        range_flush(a, cur, mn, mx, smin, smax);
+    }
+    if (blockIdx.x == 0) {
+        // thread t < 8F: slot t % 8 of field t / 8 (slots 0-3 the head, 4-7 the tail)
+        for (uint32_t t = threadIdx.x; t < 8u * a.F; t += 256) {
+            const uint32_t f = t >> 3, j = t & 7u;
+            const float* xf = a.x[f];
+            const uint64_t head = ((16u - (reinterpret_cast<uintptr_t>(xf) & 15u)) & 15u) / 4u;
+            const uint64_t h = head < a.n ? head : a.n;
+            const uint64_t tail0 = h + 4 * ((a.n - h) / 4);
+            const uint64_t i = j < 4 ? (uint64_t)j : tail0 + (j - 4);
+            const bool live = j < 4 ? i < h : i < a.n;
+            if (live && __builtin_isfinite(xf[i])) {
+                const int k = order_key(xf[i]);
+                atomicMin(&a.keys[f], k);
+                atomicMax(&a.keys[a.F + f], k);
+            }
+        }
     }
 }
 
@@ -491,19 +526,50 @@ hipError_t launch_bound_check(const float* const* orig, const float* const* reco
     return hipGetLastError();
 }
 
-hipError_t launch_field_range(const float* const* x, uint64_t n, uint32_t F, int* keys,
-                              hipStream_t s) {
+uint32_t device_cu_count() {
+    constexpr int kDevices = 64;
+    static std::atomic<int> cached[kDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return 256;
+    int c = cached[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c <= 0)
+            c = 256;
+        cached[dev].store(c, std::memory_order_relaxed);
+    }
+    return (uint32_t)c;
+}
+
+hipError_t launch_field_range_shape(const float* const* x, uint64_t n, uint32_t F, int* keys,
+                                    uint32_t groups_per_cu, uint32_t unroll, hipStream_t s) {
     RangeArgs a{};
     for (uint32_t f = 0; f < F; f++) a.x[f] = x[f];
     a.n = n;
     a.F = F;
     a.keys = keys;
-    // about two 4-vector sweeps per lane at full size; at least one workgroup
-    uint64_t groups = (n / 4 + 4095) / 4096;
-    if (groups > 2048) groups = 2048;
+    const uint64_t chunk = (uint64_t)unroll * 256;
+    a.cpf = (n / 4 + chunk - 1) / chunk;
+    if (a.cpf == 0) a.cpf = 1;  // workgroup 0 still takes the loose elements
+    uint64_t groups = (uint64_t)groups_per_cu * device_cu_count();
+    if (groups > a.cpf * F) groups = a.cpf * F;  // never more than the chunks
     if (groups == 0) groups = 1;
-    hipLaunchKernelGGL(field_range_kernel, dim3((uint32_t)groups, F), dim3(256), 0, s, a);
+    const dim3 g((uint32_t)groups), b(256);
+    switch (unroll) {
+        case 2: hipLaunchKernelGGL(field_range_kernel<2>, g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL(field_range_kernel<4>, g, b, 0, s, a); break;
+        case 8: hipLaunchKernelGGL(field_range_kernel<8>, g, b, 0, s, a); break;
+        case 16: hipLaunchKernelGGL(field_range_kernel<16>, g, b, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_field_range(const float* const* x, uint64_t n, uint32_t F, int* keys,
+                              hipStream_t s) {
+    // two workgroups per CU, four 16-byte loads in flight per lane: the best
+    // shape of a sweep over 1-16 workgroups per CU and 2-16 loads (64M x 6)
+    return launch_field_range_shape(x, n, F, keys, 2, 4, s);
 }
 
 }  // namespace gpz

@@ -39,6 +39,12 @@ struct gpz_batch {
     uint64_t* d_total = nullptr;
     uint64_t* d_sizes = nullptr;   // stream size per job
     uint32_t* d_errors = nullptr;  // decode error flag per job
+    // blocks left to the generic encoder (their grid needs 64-bit steps):
+    // one list per job inside d_defer, its length and the job's wide-record
+    // flag (d_dcount and d_wide are contiguous, cleared by one fill)
+    uint32_t* d_defer = nullptr;
+    uint32_t* d_dcount = nullptr;
+    uint32_t* d_wide = nullptr;
     // Pinned host image of the job tables and launch descriptor (the first
     // upload_bytes of `tables`), uploaded with one asynchronous copy per bind;
     // `uploaded` marks the last copy, after which the image may be rewritten.
@@ -119,7 +125,11 @@ int to_status(hipError_t e) { return e == hipSuccess ? GPZ_OK : GPZ_EDEVICE; }
 int enqueue_compress(gpz_batch* b, hipStream_t s) {
     int rc = to_status(launch_fill_u32(b->d_counters, 0u, 1, s));
     if (rc == GPZ_OK) rc = to_status(launch_fill_u32(b->d_supsum, 0u, b->max_super + 1, s));
+    if (rc == GPZ_OK) rc = to_status(launch_fill_u32(b->d_dcount, 0u, 2ull * b->max_jobs, s));
     if (rc == GPZ_OK) rc = to_status(launch_encode_batch(b->d_enc, b->d_launch, b->shape, s));
+    if (rc == GPZ_OK)
+        rc = to_status(launch_encode_generic_batch(b->d_enc, b->d_launch, b->p.block_size,
+                                                   (uint32_t)b->max_blocks, s));
     if (rc == GPZ_OK) rc = to_status(launch_scan_batch(b->d_scan, b->d_launch, b->shape, s));
     if (rc == GPZ_OK) rc = to_status(launch_copy_batch(b->d_copy, b->d_launch, b->shape, s));
     return rc;
@@ -225,6 +235,10 @@ int bind(gpz_batch* b, const gpz_job* jobs, uint32_t njobs, void* d_ws, uint64_t
         e.lens = b->d_lens + blk_at;
         e.supsum = b->d_supsum + sup_at;
         e.perm = nullptr;
+        e.defer = b->d_defer + blk_at;
+        e.defer_count = b->d_dcount + j;
+        e.wide_flag = b->d_wide + j;
+        sa.wide_flag = e.wide_flag;
         sa.supsum = e.supsum;
         sa.supoff = b->d_supoff + sup_at;
         sa.total_bytes = b->d_total + j;
@@ -372,6 +386,8 @@ int gpz_batch_create(gpz_batch** out, const gpz_job* jobs, uint32_t njobs, const
     const uint64_t o_tot = take(8ull * mj);
     const uint64_t o_sizes = take(8ull * mj);
     const uint64_t o_err = take(4ull * mj);
+    const uint64_t o_defer = take(4 * mb + 4);
+    const uint64_t o_dcount = take(8ull * mj);  // counts, then wide flags
     if (hipMalloc(&b->tables, o) != hipSuccess) {
         delete b;
         return GPZ_ENOMEM;
@@ -392,6 +408,9 @@ int gpz_batch_create(gpz_batch** out, const gpz_job* jobs, uint32_t njobs, const
     b->d_total = reinterpret_cast<uint64_t*>(base + o_tot);
     b->d_sizes = reinterpret_cast<uint64_t*>(base + o_sizes);
     b->d_errors = reinterpret_cast<uint32_t*>(base + o_err);
+    b->d_defer = reinterpret_cast<uint32_t*>(base + o_defer);
+    b->d_dcount = reinterpret_cast<uint32_t*>(base + o_dcount);
+    b->d_wide = b->d_dcount + mj;
     b->upload_bytes = o_cnt;  // the tables and launch descriptor come first
     if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess ||

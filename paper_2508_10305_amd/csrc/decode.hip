@@ -11,7 +11,7 @@
 // between its lanes is ordered by wave_lds_sync().  Every read of the record
 // is checked against its length first; a malformed record sets the error
 // flag and the block is skipped.
-#include "gpz_internal.h"
+#include "generic_block.h"
 
 namespace gpz {
 namespace {
@@ -97,7 +97,9 @@ __device__ __forceinline__ bool header_bad(const DecodeArgs& a, uint32_t lane) {
         uint32_t want = expect[0];
 #pragma unroll
         for (uint32_t k = 1; k < kHeaderWords; k++) want = lane == k ? expect[k] : want;
-        if (a.in[lane] != want) bad = true;
+        // word 1 may carry the wide-record flag (a float32 stream otherwise)
+        const uint32_t got = lane == 1 ? (a.in[lane] & ~(2u << 16)) : a.in[lane];
+        if (got != want) bad = true;
     }
     return bad;
 }
@@ -122,9 +124,18 @@ struct DecodeSmem {
     uint32_t buf[kBuf];
 };
 
+// The decoder's LDS: its own buffer, or the generic record decoder's when a
+// record holds a field coded with 64-bit steps.
+template <int ITEMS>
+union DecodeShared {
+    DecodeSmem<ITEMS> fast;
+    GenDecodeSmem<64 * ITEMS> wide;
+};
+
 template <int ITEMS>
 __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
-                                             DecodeSmem<ITEMS>& sm) {
+                                             DecodeShared<ITEMS>& shared) {
+    DecodeSmem<ITEMS>& sm = shared.fast;
     constexpr uint32_t B = 64 * ITEMS;
     constexpr uint32_t G = ITEMS / 4;  // 16-byte groups per lane
     uint32_t* words = sm.buf;
@@ -170,6 +181,17 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
     const uint32_t h0 = len ? rec[0] : 0u;
     const uint32_t mode = h0 & 3u;
 
+    if (len != 0 && mode == 0 && (h0 >> 31)) {
+        // a field coded with 64-bit steps (Sec. 5.3): the generic record
+        // decoder, run by this wave, when the header announces such records
+        // (corrupt otherwise)
+        if (!((a.in[1] >> 17) & 1u)) {
+            if (lane == 0) *a.err = 1u;
+            return;
+        }
+        gen_decode_record<64 * ITEMS, 64, false>(a, b, rec, len, shared.wide);
+        return;
+    }
     if (len == 0 || mode > 1) {
         if (lane == 0) *a.err = 1u;
         return;
@@ -381,8 +403,8 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
 }
 
 template <int ITEMS>
-__global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
-    __shared__ __align__(16) DecodeSmem<ITEMS> sm;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void decode_blocks(DecodeArgs a) {
+    __shared__ __align__(16) DecodeShared<ITEMS> sm;
     decode_block<ITEMS>(a, blockIdx.x, sm);
 }
 
@@ -391,7 +413,7 @@ __global__ __launch_bounds__(64) void decode_blocks(DecodeArgs a) {
 template <int ITEMS>
 __global__ __launch_bounds__(64) void decode_batch(const DecodeArgs* __restrict__ jobs,
                                                    const BatchLaunch* __restrict__ L) {
-    __shared__ __align__(16) DecodeSmem<ITEMS> sm;
+    __shared__ __align__(16) DecodeShared<ITEMS> sm;
     const uint32_t total = L->total_blocks, njobs = L->njobs, tile = L->tile;
     const uint32_t* prefix = L->block_prefix;
     for (;;) {
@@ -413,7 +435,7 @@ __global__ __launch_bounds__(64) void decode_batch(const DecodeArgs* __restrict_
 template <int ITEMS>
 __global__ __launch_bounds__(64) void decode_batch_direct(const DecodeArgs* __restrict__ jobs,
                                                           const BatchLaunch* __restrict__ L) {
-    __shared__ __align__(16) DecodeSmem<ITEMS> sm;
+    __shared__ __align__(16) DecodeShared<ITEMS> sm;
     const uint32_t g = blockIdx.x;
     if (g >= L->total_blocks) return;
     const uint32_t* prefix = L->block_prefix;

@@ -48,9 +48,9 @@ __device__ __forceinline__ uint32_t pad_addr(uint32_t p) {
 // error of xr = fma(q, 2eb, lo) is below eb (which bounds the exact error
 // strictly), otherwise it is an outlier stored verbatim.
 __device__ __forceinline__ uint32_t quantize(float x, float lo, float inv, float twoeb, float eb,
-                                             bool& outlier) {
+                                             bool& outlier, bool& in) {
     float t = (x - lo) * inv;
-    bool in = (t >= 0.0f) && (t <= kQMax);
+    in = (t >= 0.0f) && (t <= kQMax);
     uint32_t q = in ? (uint32_t)__builtin_rintf(t) : 0u;
     float xr = __builtin_fmaf((float)q, twoeb, lo);
     bool ok = in && (__builtin_fabsf(xr - x) < eb);
@@ -82,11 +82,14 @@ __device__ __forceinline__ void load_block(const float* __restrict__ x, uint64_t
 }
 
 // A field of the block after quantization: its minimum lo, the largest code
-// over the block's particles, and whether no value is an outlier.
+// over the block's particles, whether no value is an outlier, and whether a
+// finite value lies beyond 2^24 - 1 grid steps (the field then needs 64-bit
+// steps, Sec. 5.3, which the generic encoder takes).
 struct FieldCodes {
     float lo;
     uint32_t qmax;
     bool clean;
+    bool wide;
 };
 
 // Quantize one field of the block (Sec. 4.1).  Codes are returned as
@@ -144,19 +147,21 @@ __device__ __forceinline__ FieldCodes quantize_field(const float (&v)[ITEMS], ui
         q[j] = valid ? (uint32_t)(r + r) : 0u;
     }
     uint32_t qmax = wave_max_u32(rmax <= kQMax ? (uint32_t)rmax : 0xFFFFFFFFu);
-    if (__all(emax < eb) && qmax <= 0xFFFFFFu) return {lo, qmax, true};
+    if (__all(emax < eb) && qmax <= 0xFFFFFFu) return {lo, qmax, true, false};
     // some value is an outlier: the quantizer's steps, value by value
     uint32_t mx = 0;
+    bool far = false;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const bool valid = FULL || lane * ITEMS + j < nb;
-        bool o;
-        const uint32_t qq = quantize(v[j], lo, inv, twoeb, eb, o);
+        bool o, in;
+        const uint32_t qq = quantize(v[j], lo, inv, twoeb, eb, o, in);
         q[j] = valid ? (qq << 1) | (uint32_t)o : 0u;
         mx = max(mx, valid ? qq : 0u);
+        far = far || (valid && !in && __builtin_isfinite(v[j]));
     }
     qmax = wave_max_u32(mx);
-    return {lo, qmax, false};
+    return {lo, qmax, false, __any(far) != 0};
 }
 
 // Fixed-length packing (Sec. 4.3): value i of `count` values of width w
@@ -564,6 +569,12 @@ __device__ __forceinline__ void place_record(const EncodeArgs& a, uint32_t b, co
     if (b == a.nblocks - 1) publish_size(a, 4 * (off + len), lane);
 }
 
+// Leaves block b to the generic encoder (its record, length, superblock sum
+// and permutation are all written there).
+__device__ __forceinline__ void defer_block(const EncodeArgs& a, uint32_t b, uint32_t lane) {
+    if (lane == 0) a.defer[atomicAdd(a.defer_count, 1u)] = b;
+}
+
 template <int ITEMS, bool FULL, bool SINGLE>
 __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, uint32_t nb,
                                              uint32_t* kvbuf, uint32_t* work) {
@@ -618,6 +629,15 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) qo[e][j] = 0;
         }
+    }
+
+    // A field whose grid needs more than 24 bits: the generic encoder codes
+    // the block (three-step compaction); the single pass, which cannot wait
+    // for it, stores the block raw.
+    bool wide = ck[0].wide || ck[1].wide || ck[2].wide || co[0].wide || co[1].wide || co[2].wide;
+    if (!SINGLE && wide) {
+        defer_block(a, b, lane);
+        return;
     }
 
     // Linearised segment ID (axis 0 most significant), packed with the index.
@@ -695,7 +715,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 
     // ---- arrays in record order: gaps, counts, then one section per field
     uint32_t pos = 2;
-    bool over = false;
+    bool over = wide;  // (single pass only: such a block is stored raw)
     for (uint32_t arr = 0; arr < 2 + F; arr++) {
         uint32_t vals[ITEMS];
         uint32_t w, count, nout = 0;
@@ -745,9 +765,14 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
                     float x[ITEMS];
                     load_block<ITEMS, FULL>(a.x[f], base, nb, lane, x);
                     c = quantize_field<ITEMS, FULL>(x, nb, lane, a.inv[f], a.twoeb[f], a.eb[f], q);
+                    wide = wide || c.wide;
                     stage_codes<ITEMS, false>(q, width, c.clean, mine, vmax, no);
                     break;
                 }
+            }
+            if (wide) {
+                over = true;
+                break;
             }
             const float lo = c.lo;
             w = bit_width(key ? wave_max_u32(vmax) : c.qmax);
@@ -798,6 +823,10 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         wave_lds_sync();  // staging reads done before the next field overwrites it
     }
 
+    if (!SINGLE && wide) {
+        defer_block(a, b, lane);
+        return;
+    }
     const bool raw = over || pos >= cap;
     if (raw) {
         // Raw form: the block's floats verbatim, field-major, input order.

@@ -31,7 +31,7 @@ __host__ __device__ inline uint32_t bit_width(uint32_t v) { return v ? 32u - (ui
 // ------------------------------------------------------------ kernel arguments
 
 struct EncodeArgs {
-    const float* x[kMaxFields];
+    const float* x[kMaxFields];  // float32 fields, or float64 ones (f64: read as double*)
     float eb[kMaxFields];
     float twoeb[kMaxFields];
     float inv[kMaxFields];
@@ -52,6 +52,12 @@ struct EncodeArgs {
     uint64_t prefix;       // words before the record area
     uint64_t* total_bytes; // stream size, written by the last block
     uint64_t* ext_bytes;   // nullable second destination of the size
+    uint32_t f64;          // the fields are float64
+    // blocks whose grid needs 64-bit steps, left by the wave-per-block
+    // encoder to the generic one (three-step compaction only)
+    uint32_t* defer;       // nblocks entries
+    uint32_t* defer_count; // zeroed before the launch
+    uint32_t* wide_flag;   // set when a record codes a field with 64-bit steps (zeroed before)
 };
 
 // Three-step compaction (Sec. 4.4): scan of the superblock sums, then the copy.
@@ -68,6 +74,8 @@ struct ScanArgs {
     uint64_t n;
     uint32_t F, B, K, KF, nblocks;
     uint32_t eb_bits[kMaxFields];
+    uint32_t f64;               // header flag 1: float64 fields
+    const uint32_t* wide_flag;  // nonzero: header flag 2 (a record has a wide field)
 };
 
 struct CopyArgs {
@@ -92,6 +100,7 @@ struct DecodeArgs {
     uint64_t prefix;       // words before the record area
     uint32_t* err;         // set nonzero on a malformed record
     uint32_t exact;        // in_words is the exact stream length (else an upper bound)
+    uint32_t f64;          // float64 stream: y[f] are double* (generic decoder only)
 };
 
 // ------------------------------------------------------------ wave64 primitives
@@ -210,6 +219,57 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t f2u(float f) { return __float_as_uint(f); }
 __device__ __forceinline__ float u2f(uint32_t u) { return __uint_as_float(u); }
 
+// Exclusive scan of the per-superblock record sizes (Sec. 4.4) by one
+// workgroup of T lanes (there are only ceil(nblocks / 64) superblocks):
+// thread t sums a contiguous chunk, the
+// chunk totals are scanned in LDS, then each thread writes its offsets.  The
+// last thread publishes the stream size; when the stream fits the output
+// buffer the workgroup also writes the header and the eb table.
+template <uint32_t T>
+__device__ __forceinline__ void scan_superblocks(const ScanArgs& a, uint64_t* part) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t ns = a.nsuper;
+    const uint32_t chunk = (ns + T - 1) / T;
+    const uint32_t lo = t * chunk;
+    const uint32_t hi = lo + chunk < ns ? lo + chunk : ns;
+    uint64_t sum = 0;
+    for (uint32_t i = lo; i < hi; i++) sum += a.supsum[i];
+    part[t] = sum;
+    __syncthreads();
+    for (uint32_t o = 1; o < T; o <<= 1) {
+        uint64_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint64_t run = part[t] - sum;
+    for (uint32_t i = lo; i < hi; i++) {
+        a.supoff[i] = run;
+        run += a.supsum[i];
+    }
+    const uint64_t bytes = 4 * (a.prefix + part[T - 1]);
+    if (t == T - 1) {
+        *a.total_bytes = bytes;
+        if (a.ext_bytes) *a.ext_bytes = bytes;
+    }
+    if (bytes <= a.capacity) {
+        if (t == 0) {
+            a.out[0] = kMagic;
+            // flags: 1 float64 fields, 2 some record has a wide field
+            const uint32_t wide = a.wide_flag && *a.wide_flag ? 2u : 0u;
+            a.out[1] = kVersion | (((a.f64 ? 1u : 0u) | wide) << 16);
+            a.out[2] = (uint32_t)(a.n & 0xFFFFFFFFu);
+            a.out[3] = (uint32_t)(a.n >> 32);
+            a.out[4] = a.F;
+            a.out[5] = a.B;
+            a.out[6] = a.K | (a.KF << 8);
+            a.out[7] = a.nblocks;
+        }
+        uint32_t* ebt = a.out + kHeaderWords + 2 * nsuper_of(a.nblocks);
+        for (uint32_t f = t; f < a.F; f += T) ebt[f] = a.eb_bits[f];
+    }
+}
+
 // ------------------------------------------------------------ launchers
 
 // single_pass: one launch that also places the records (look-back);
@@ -228,6 +288,24 @@ hipError_t launch_stream_stats(const uint32_t* in, uint64_t in_words, uint64_t n
                                uint32_t* err, hipStream_t s);
 hipError_t launch_field_range(const float* const* x, uint64_t n, uint32_t F, int* keys,
                               hipStream_t s);
+// The same with an explicit launch shape: workgroups per CU and 16-byte
+// loads in flight per lane (2, 4, 8 or 16).
+hipError_t launch_field_range_shape(const float* const* x, uint64_t n, uint32_t F, int* keys,
+                                    uint32_t groups_per_cu, uint32_t unroll, hipStream_t s);
+// Generic 256-lane-per-block kernels (float64 fields, fields needing 64-bit
+// grid steps, any block size).  deferred_only: the blocks the wave-per-block
+// encoder left on its list; otherwise every block.  The decoder takes every
+// block (the wave-per-block decoder decodes records with a wide field
+// itself).
+hipError_t launch_encode_generic(const EncodeArgs& a, bool deferred_only, hipStream_t s);
+// The deferred blocks, then the length scan in the same launch (the last
+// workgroup to finish its share scans; *done is zero before the launch).
+hipError_t launch_encode_deferred_then_scan(const EncodeArgs& a, const ScanArgs& sa,
+                                            uint32_t* done, hipStream_t s);
+hipError_t launch_decode_generic(const DecodeArgs& a, hipStream_t s);
+// Compute units of the current device (queried once per device, 256 if the
+// query fails).
+uint32_t device_cu_count();
 
 // ------------------------------------------------------------ batched form
 // Many snapshots in one launch per stage.  Job tables live in device memory;
@@ -279,6 +357,10 @@ hipError_t launch_scan_batch(const ScanArgs* jobs, const BatchLaunch* L, const B
                              hipStream_t s);
 hipError_t launch_copy_batch(const CopyArgs* jobs, const BatchLaunch* L, const BatchShape& S,
                              hipStream_t s);
+// Batched form of the deferred-block encoder: a fixed grid that walks every
+// job's list (max_blocks: the batch's block capacity).
+hipError_t launch_encode_generic_batch(const EncodeArgs* jobs, const BatchLaunch* L, uint32_t B,
+                                       uint32_t max_blocks, hipStream_t s);
 hipError_t launch_decode_batch(const DecodeArgs* jobs, const BatchLaunch* L,
                                const BatchShape& S, hipStream_t s);
 

@@ -40,9 +40,11 @@ def test_library_exports_every_declared_symbol(gpz):
 
 
 def test_sizes_match_oracle(gpz, orc):
+    L = gpz.lib()
     for n in [0, 1, 1023, 1024, 1025, 10 ** 6]:
         for F in [1, 3, 6]:
             assert gpz.max_compressed_bytes(n, F) == orc.max_bytes(n, F, 1024)
+            assert L.gpz_max_compressed_bytes_f64(n, F, None) == orc.max_bytes(n, F, 1024, True)
     assert gpz.compress_workspace_bytes(10 ** 6, 3) >= 4 * 3 * 10 ** 6
 
 
@@ -60,7 +62,8 @@ def test_inspect_parses_oracle_stream(gpz, orc):
     x = [np.random.default_rng(1).random(3000).astype(np.float32) for _ in range(4)]
     s, _ = orc.compress(x, 1e-3, K=2, KF=2)
     info = gpz.inspect(s[:32].tobytes())
-    assert info == dict(n=3000, nfields=4, block_size=1024, seg_bits=2, key_fields=2, nblocks=3)
+    assert info == dict(n=3000, nfields=4, block_size=1024, seg_bits=2, key_fields=2, nblocks=3,
+                        flags=0)
     bad = bytearray(s[:32].tobytes())
     bad[0] ^= 1
     with pytest.raises(gpz.GpzError):
@@ -84,8 +87,14 @@ def test_invalid_arguments_rejected_before_device_work(gpz):
         assert L.gpz_compress(*args(p, np.array([e], np.float32))) == gpz.GPZ_EINVAL
     assert L.gpz_compress(*args(p, eb, F=0)) == gpz.GPZ_EINVAL
     assert L.gpz_compress(*args(p, eb, F=65)) == gpz.GPZ_EINVAL
-    p512 = gpz.params(1, block_size=64)
-    assert L.gpz_compress(*args(p512, eb)) == gpz.GPZ_EUNSUPPORTED
+    # block sizes outside 256..2048 run the generic kernels, but not the
+    # single-pass compaction; float64 fields neither
+    p64 = gpz.params(1, block_size=64, single_pass=True)
+    assert L.gpz_compress(*args(p64, eb)) == gpz.GPZ_EUNSUPPORTED
+    p1 = gpz.params(1, single_pass=True)
+    assert L.gpz_compress_f64(*args(p1, eb)) == gpz.GPZ_EUNSUPPORTED
+    assert L.gpz_max_compressed_bytes_f64(1000, 3, None) == \
+        2 * L.gpz_max_compressed_bytes(1000, 3, None) - 4 * (8 + 2 + 3 + 1 + 1)
     assert L.gpz_decompress(None, 100, None, 10, 1, None, 0, None) == gpz.GPZ_EINVAL
 
 
@@ -96,8 +105,8 @@ def test_strerror(gpz):
 
 def test_timing_kinds_mask(gpz):
     L = gpz.lib()
-    assert L.gpz_set_timing_kinds(1 << 5) == gpz.GPZ_EINVAL  # no kind 5
-    assert L.gpz_set_timing_kinds(0x1F) == gpz.GPZ_OK
+    assert L.gpz_set_timing_kinds(1 << 6) == gpz.GPZ_EINVAL  # no kind 6
+    assert L.gpz_set_timing_kinds(0x3F) == gpz.GPZ_OK
     assert L.gpz_set_timing_kinds(0) == gpz.GPZ_OK
     with pytest.raises(ValueError):
         gpz.set_timing(True, kinds=("no such kernel",))
