@@ -225,6 +225,18 @@ int gpz_stream_stats(const void *d_in, uint64_t in_bytes, uint64_t n, uint32_t n
 int gpz_field_range(const float *const *h_fields, uint64_t n, uint32_t nfields, float *h_minmax,
                     void *d_ws, uint64_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code that sets up HIP graph
+ * captures, tight serving loops, harnesses that forbid hipMalloc):
+ * gpz_field_range with no workspace argument and no allocation of any kind.
+ * Its scratch is a library-owned device array of 2 * 64 int keys (512
+ * bytes; at most 64 fields, GPZ_EINVAL beyond), one per GPU, held until the
+ * process ends and reset by the call itself.  Every call on one GPU shares
+ * that GPU's array, so calls that overlap on one GPU (from other host
+ * threads or on other streams) race: the caller serializes them.
+ * Synchronizes `stream`. */
+int gpz_field_range_noalloc(const float *const *h_fields, uint64_t n, uint32_t nfields,
+                            float *h_minmax, void *stream);
+
 /* Relative bound -> absolute bound of one field: (float)(rel * (hi - lo))
  * computed in double; below 2^-120 (constant field) it is rel itself; above
  * 2^120 it is capped. */

@@ -25,7 +25,7 @@ EXPORTS = (
     "gpz_decompress_workspace_bytes", "gpz_compress", "gpz_compress_async", "gpz_decompress",
     "gpz_decompress_async", "gpz_compress_f64", "gpz_max_compressed_bytes_f64",
     "gpz_compress_workspace_bytes_f64", "gpz_decompress_f64", "gpz_stats_workspace_bytes", "gpz_bound_check", "gpz_error_stats",
-    "gpz_stream_stats", "gpz_field_range", "gpz_rel_to_abs", "gpz_inspect",
+    "gpz_stream_stats", "gpz_field_range", "gpz_field_range_noalloc", "gpz_rel_to_abs", "gpz_inspect",
     "gpz_set_timing", "gpz_set_timing_kinds", "gpz_timing_collect", "gpz_strerror",
     "gpz_default_batch_config",
     "gpz_batch_workspace_bytes", "gpz_batch_create", "gpz_batch_rebind", "gpz_batch_compress",
@@ -123,6 +123,8 @@ def _lib():
         L.gpz_stream_stats.restype = ctypes.c_int
         L.gpz_field_range.argtypes = [vp, u64, u32, vp, vp, u64, vp]
         L.gpz_field_range.restype = ctypes.c_int
+        L.gpz_field_range_noalloc.argtypes = [vp, u64, u32, vp, vp]
+        L.gpz_field_range_noalloc.restype = ctypes.c_int
         L.gpz_rel_to_abs.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
         L.gpz_rel_to_abs.restype = ctypes.c_float
         L.gpz_inspect.argtypes = [vp, u64, ctypes.POINTER(Info)]
@@ -434,6 +436,19 @@ def field_range(fields: Sequence, stream=None, ws=None) -> np.ndarray:
                                 mm.ctypes.data_as(ctypes.c_void_p), *_ws_args(ws),
                                 _stream_handle(stream))
     _check(rc, "gpz_field_range")
+    return mm.reshape(F, 2)
+
+
+def field_range_noalloc(fields: Sequence, stream=None) -> np.ndarray:
+    """As field_range, through the allocation-free entry point (library-owned
+    per-GPU scratch; calls on one GPU must not overlap)."""
+    F = len(fields)
+    n = _check_fields(fields)
+    mm = np.zeros(2 * F, np.float32)
+    rc = _lib().gpz_field_range_noalloc(ctypes.cast(_ptr_array(fields), ctypes.c_void_p), n, F,
+                                        mm.ctypes.data_as(ctypes.c_void_p),
+                                        _stream_handle(stream))
+    _check(rc, "gpz_field_range_noalloc")
     return mm.reshape(F, 2)
 
 

@@ -3,12 +3,20 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "gpz.h"
 #include "gpz_internal.h"
 
 using namespace gpz;
+
+// Scratch of gpz_field_range_noalloc: the 2F order-preserving minimum and
+// maximum keys of up to kMaxFields fields (512 bytes).  Each GPU holds its
+// own copy for the life of the process.  In host code `scratch` only names
+// the symbol: kernels are given its device address, looked up once per
+// device (noalloc_scratch).
+static __device__ __align__(256) int scratch[2 * kMaxFields];
 
 namespace {
 
@@ -315,6 +323,26 @@ int field_range_into(const float* const* h_fields, uint64_t n, uint32_t F, int* 
     else (void)hipStreamSynchronize(s);  // queued kernels may still use the keys
     if (rc) return rc;
     for (uint32_t f = 0; f < F; f++) range_from_keys(h[f], h[F + f], &h_minmax[2 * f], &h_minmax[2 * f + 1]);
+    return GPZ_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device; the symbol lookup runs
+// on the first call per device, with that device current.
+int noalloc_scratch(int** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GPZ_EDEVICE;
+    if (dev < 0 || dev >= kMaxDevices) return GPZ_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GPZ_EDEVICE;
+        g_scratch_ptr[dev] = static_cast<int*>(p);
+    }
+    *out = g_scratch_ptr[dev];
     return GPZ_OK;
 }
 
@@ -649,6 +677,20 @@ int gpz_field_range(const float* const* h_fields, uint64_t n, uint32_t nfields, 
     rc = field_range_into(h_fields, n, nfields, reinterpret_cast<int*>(ws), h_minmax, s);
     if (owned) (void)hipFree(ws);
     return rc;
+}
+
+int gpz_field_range_noalloc(const float* const* h_fields, uint64_t n, uint32_t nfields,
+                            float* h_minmax, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nfields < 1 || nfields > kMaxFields || !h_minmax) return GPZ_EINVAL;
+    if (n > 0 && !h_fields) return GPZ_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < nfields; f++)
+        if (!h_fields[f]) return GPZ_EINVAL;
+    int* keys = nullptr;
+    int rc = noalloc_scratch(&keys);
+    if (rc) return rc;
+    // the keys are reset by fill kernels inside field_range_into before use
+    return field_range_into(h_fields, n, nfields, keys, h_minmax, s);
 }
 
 float gpz_rel_to_abs(float rel, float lo, float hi) {
