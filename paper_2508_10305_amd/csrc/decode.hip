@@ -161,7 +161,11 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
     const uint32_t first = sb * kSuper;
     const uint64_t sup_off = (uint64_t)sup[2 * sb] | ((uint64_t)sup[2 * sb + 1] << 32);
     const uint64_t mine = (first + lane < b) ? (uint64_t)lens[first + lane] : 0ull;
-    const uint64_t off = sup_off + wave_sum_u64(mine);
+    const uint64_t sum = sup_off + wave_sum_u64(mine);
+    // every lane holds the same sum: taken from lane 0 it is a scalar, and so
+    // are the record pointer and every header word read through it
+    const uint64_t off = ((uint64_t)readlane((uint32_t)(sum >> 32), 0) << 32) |
+                         (uint64_t)readlane((uint32_t)sum, 0);
     const uint32_t len = lens[b];
     bool bad = sup_off > rec_total || off > rec_total || (uint64_t)len > rec_total - off;
     if (b == 0 && (sup[0] | sup[1]) != 0u) bad = true;
@@ -403,7 +407,7 @@ __device__ __forceinline__ void decode_block(const DecodeArgs& a, uint32_t b,
 }
 
 template <int ITEMS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void decode_blocks(DecodeArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void decode_blocks(DecodeArgs a) {
     __shared__ __align__(16) DecodeShared<ITEMS> sm;
     decode_block<ITEMS>(a, blockIdx.x, sm);
 }
