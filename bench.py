@@ -59,6 +59,184 @@ def measured_traffic():
         return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def kernel_times(gpz, torch, fn, steps):
+    """Average per-launch ms of every kernel kind over `steps` calls of fn()."""
+    gpz.set_timing(True)
+    gpz.timing_collect()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    gpz.set_timing(False)
+    return {k: (v[0] / v[1] if v[1] else 0.0) for k, v in gpz.timing_collect().items()}
+
+
+def workload_figures(gpz, torch, kind, n, seed, rel, steps, warmup):
+    """Plain-form figures of one more workload (molecular-dynamics-like or
+    LiDAR-like) at a relative bound: step time, compress / decompress rates,
+    the encoder's and decoder's HBM roofline fractions, ratio, largest error
+    relative to the bound (checked below 1 for every field)."""
+    from paper_2508_10305_amd import synth
+    host = synth.make(kind, n, seed)
+    fields = [torch.from_numpy(f).cuda() for f in host]
+    del host
+    n, F = fields[0].numel(), len(fields)
+    S = 4 * n * F
+    eb = gpz.rel_ebs(fields, rel)
+    p = gpz.params(F)
+    comp = gpz.Compressor(n, F, p)
+    outs = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(F)]
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream, perm = comp.compress(fields, eb, want_perm=True)
+    C = int(stream.numel())
+    gpz.decompress(stream, n, F, out=outs)
+    est = gpz.error_stats(fields, outs, eb, perm=perm)
+    assert int(est["violations"].sum()) == 0, f"{kind}: bound violated"
+    del perm
+
+    def step():
+        comp.compress_async(fields, eb)
+        gpz.decompress_async(comp.out, n, F, outs, err, p)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    ms = e0.elapsed_time(e1) / steps
+    kt = kernel_times(gpz, torch, step, steps)
+    nb = (n + p.block_size - 1) // p.block_size
+    rec = C - 4 * (8 + 2 * ((nb + 63) // 64) + F + nb)
+    t_c = kt["prepare"] + kt["encode"] + kt["scan"] + kt["copy"]
+    t_d = kt["decode"] + kt["generic"]
+    out = {"n": n, "fields": F, "rel_eb": rel, "ms_per_step": round(ms, 4),
+           "GBps": round(2 * S / (ms * 1e-3) / 1e9, 1),
+           "compress_GBps": round(S / (t_c * 1e-3) / 1e9, 1),
+           "decompress_GBps": round(S / (t_d * 1e-3) / 1e9, 1),
+           "encoder_ms": round(kt["encode"], 4), "decoder_ms": round(kt["decode"], 4),
+           "encoder_roofline_frac": round((S + rec) / (kt["encode"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "decoder_roofline_frac": round((C + S) / (kt["decode"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "compression_ratio": round(S / C, 4),
+           "max_abs_err_over_eb": float((est["max_abs_err"] / eb.astype(np.float64)).max()),
+           "aggregate_psnr_db": round(est["psnr"], 3)}
+    del comp, fields, outs, stream
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_figures(gpz, torch, steps):
+    """Batched form (256 snapshots, as bench.py --form batched) at the launch
+    shape the autotuner picked on this GPU: round time and rate beside the
+    loop of plain per-snapshot launches of the same jobs; every stream is
+    compared with the plain one."""
+    from paper_2508_10305_amd import synth
+    from paper_2508_10305_amd.batch import Batch, default_config
+    specs = synth.batch_specs(256, seed=4)
+    fields = [synth.clusters_device(sp["n"], sp["seed"], sp["clusters"],
+                                    extra_fields=sp["fields"] - 3) for sp in specs]
+    S = sum(4 * sp["n"] * sp["fields"] for sp in specs)
+    ebs = [sp["eb"] for sp in specs]
+    p = gpz.params(3)
+    outs = [torch.empty(gpz.max_compressed_bytes(sp["n"], sp["fields"], p), dtype=torch.uint8,
+                        device="cuda") for sp in specs]
+    decs = [[torch.empty(sp["n"], dtype=torch.float32, device="cuda") for _ in range(sp["fields"])]
+            for sp in specs]
+    comps = [gpz.Compressor(sp["n"], sp["fields"], p) for sp in specs]
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def plain_round():
+        for j, sp in enumerate(specs):
+            comps[j].compress_async(fields[j], ebs[j])
+            gpz.decompress_async(comps[j].out, sp["n"], sp["fields"], decs[j], err, p)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    ms_plain = timed(plain_round, 3)
+    ref = []
+    for j, sp in enumerate(specs):
+        s_, _ = comps[j].compress(fields[j], ebs[j])
+        ref.append(s_.clone())
+    del comps
+    ws = torch.empty(Batch.workspace_bytes(fields, ebs, outs, decs, p), dtype=torch.uint8,
+                     device="cuda")
+    cfg = default_config()
+    cfg.grid, cfg.tile, cfg.use_graph = 0, 1, 1  # the autotuner's pick on MI355X
+    b = Batch(fields, ebs, outs, dec=decs, p=p, config=cfg, workspace=ws)
+
+    def rnd():
+        b.compress()
+        b.decompress()
+    ms = timed(rnd, steps)
+    sizes = b.sizes()
+    assert (b.errors() == 0).all()
+    same = all(int(sizes[j]) == ref[j].numel() and
+               bool(torch.equal(outs[j][: ref[j].numel()], ref[j])) for j in range(len(specs)))
+    C = int(sizes.sum())
+    b.close()
+    out = {"snapshots": len(specs), "bytes": S, "ms_per_round": round(ms, 4),
+           "GBps": round(2 * S / (ms * 1e-3) / 1e9, 1),
+           "roofline_frac": round(2 * (S + C) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "plain_loop_ms": round(ms_plain, 4), "speedup_vs_plain_loop": round(ms_plain / ms, 3),
+           "streams_identical_to_plain": same, "launch": {"grid": 0, "tile": 1, "graph": 1}}
+    del fields, outs, decs, ws, ref
+    torch.cuda.empty_cache()
+    return out
+
+
+def f64_figures(gpz, torch, host, rel, steps):
+    """Float64 fields (Sec. 5.1) through the generic kernels: the cosmology
+    snapshot's values widened to float64, bounds from the float32 field
+    range; compress and decompress rates of the original (float64) bytes."""
+    fields = [torch.from_numpy(f).cuda().double() for f in host]
+    n, F = fields[0].numel(), len(fields)
+    S = 8 * n * F
+    eb = gpz.rel_ebs([f.float() for f in fields], rel)
+    s, _ = gpz.compress_f64(fields, eb)
+    out = gpz.decompress_f64(s, n, F)
+    C = int(s.numel())
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(steps):
+        gpz.compress_f64(fields, eb)
+    e[1].record()
+    for _ in range(steps):
+        gpz.decompress_f64(s, n, F, out=out)
+    e[2].record()
+    torch.cuda.synchronize()
+    tc, td = e[0].elapsed_time(e[1]) / steps, e[1].elapsed_time(e[2]) / steps
+    res = {"n": n, "fields": F, "rel_eb": rel, "compression_ratio": round(S / C, 4),
+           "compress_ms": round(tc, 3), "decompress_ms": round(td, 3),
+           "compress_GBps": round(S / (tc * 1e-3) / 1e9, 1),
+           "decompress_GBps": round(S / (td * 1e-3) / 1e9, 1),
+           "note": "host-synchronous calls, each allocating its output and workspace"}
+    del fields, out, s
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +246,8 @@ def main():
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--cpu-sample-blocks", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the extra workloads (md, lidar, float64, batched) and the HBM probes")
     ap.add_argument("--form", choices=["plain", "batched", "serving", "copy", "rd"],
                     default="plain",
                     help="plain per-snapshot launch (default), batched snapshots, serving loop, "
@@ -251,13 +431,14 @@ def main():
         oracle.decompress(s_ref, m, F)
         t2 = time.perf_counter()
         cpu = {"value": round(2 * 4 * m * F / (t2 - t0) / 1e9, 5), "unit": "GB/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"first {m} particles ({m // p.block_size} blocks) x {F} fields of the "
                          f"snapshot; compress {t1 - t0:.2f}s + decompress {t2 - t1:.2f}s, "
                          f"single-threaded C"}
         # the same sample split into block-aligned chunks, one oracle call per
         # host thread (blocks are independent; ctypes releases the GIL)
         from concurrent.futures import ThreadPoolExecutor
+        # the GPU machine's CPU share for one GPU is 16 threads, whatever nproc shows
         T = max(1, min(16, len(os.sched_getaffinity(0))))
         cb = (m // p.block_size + T - 1) // T * p.block_size
         chunks = [(lo, min(m, lo + cb)) for lo in range(0, m, cb)]
@@ -271,9 +452,43 @@ def main():
             list(ex.map(one, chunks))
         t3 = time.perf_counter()
         cpu_parallel = {"value": round(2 * 4 * m * F / (t3 - t0) / 1e9, 5), "unit": "GB/s",
-                        "cores": len(chunks), "kind": "oracle",
+                        "cores": len(chunks), "kind": "oracle", "cpu_model": cpu_model(),
+                        "nproc": os.cpu_count(),
                         "sample": f"the same {m} particles in {len(chunks)} block-aligned chunks, "
                                   f"one oracle compress + decompress per thread, {t3 - t0:.2f}s"}
+
+    # whole job for a value-range-relative bound: the field range (the bound
+    # must reach the host), then compress and decompress, host-synchronous
+    for _ in range(2):
+        gpz.rel_ebs(fields, args.rel)
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ebx = gpz.rel_ebs(fields, args.rel)
+        comp.compress_async(fields, ebx)
+        gpz.decompress_async(comp.out, n, F, outs, err, p)
+    torch.cuda.synchronize()
+    rel_eb_step_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+
+    extra = {}
+    if not args.no_extras:
+        # achievable HBM rates on this GPU (streaming read and copy probes)
+        best, _ = hbm_reference(S, reps=5)
+        extra["hbm_reference"] = {"read_GBps": best["read"]["GBps"],
+                                  "copy_GBps": best["copy"]["GBps"],
+                                  "read_shape": {k: best["read"][k] for k in ("wg_per_cu", "unroll", "nt")},
+                                  "copy_shape": {k: best["copy"][k] for k in ("wg_per_cu", "unroll", "nt")}}
+        extra["f64_cosmology"] = f64_figures(gpz, torch, host, args.rel, max(3, args.steps // 4))
+        del fields, outs, comp, stream, perm
+        torch.cuda.empty_cache()
+        for key, kind, nn, seed in (("md_32M_x6", "md", 32_000_000, 2),
+                                    ("lidar_100M_x3", "lidar", 100_000_000, 3)):
+            extra[key] = workload_figures(gpz, torch, kind, nn, seed, args.rel, args.steps,
+                                          args.warmup)
+            log(f"[bench] {key}: {extra[key]}")
+        extra["batched_256"] = batched_figures(gpz, torch, args.steps)
+        log(f"[bench] batched: {extra['batched_256']}")
 
     lat.sort()
     rec = {
@@ -299,7 +514,7 @@ def main():
         "compress_GBps": round(S / (t_c * 1e-3) / 1e9, 2),
         "decompress_GBps": round(S / (t_d * 1e-3) / 1e9, 2),
         "compression_ratio": round(S / C, 4),
-        "max_abs_err_over_eb": round(float((maxerr / eb).max()), 6),
+        "max_abs_err_over_eb": float((maxerr / eb.astype(np.float64)).max()),
         "bit_rate_bits_per_value": round(8 * C / (n * F), 4),
         "aggregate_psnr_db": round(est["psnr"], 3),
         "outlier_fraction": float(outl.sum()) / (n * F),
@@ -307,6 +522,8 @@ def main():
         "kernels": kernels,
         "compaction_ab": compaction_ab,
         "field_range_ms": round(range_ms, 3),
+        "rel_eb_step_ms": round(rel_eb_step_ms, 4),
+        **extra,
         "plain_latency_ms": {"p50": round(lat[len(lat) // 2], 3),
                              "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3)},
     }
