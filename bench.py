@@ -259,6 +259,9 @@ def main():
     ap.add_argument("--batch-tile", type=int, default=0)
     ap.add_argument("--jobs", type=int, default=256, help="snapshots of the batched form")
     ap.add_argument("--requests", type=int, default=20_000, help="requests of the serving form")
+    ap.add_argument("--serve-streams", type=int, default=3,
+                    help="serving form: HIP streams running launches (one more runs the "
+                         "field ranges of relative-bound requests)")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="scales the serving request sizes (1.0: 100K-32M particles)")
     args = ap.parse_args()

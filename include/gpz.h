@@ -225,6 +225,14 @@ int gpz_stream_stats(const void *d_in, uint64_t in_bytes, uint64_t n, uint32_t n
 int gpz_field_range(const float *const *h_fields, uint64_t n, uint32_t nfields, float *h_minmax,
                     void *d_ws, uint64_t ws_bytes, void *stream);
 
+/* As gpz_field_range without any host synchronization (graph-capturable):
+ * the 2F results (as gpz_field_range returns them) land in the device array
+ * d_minmax; d_ws (required) holds at least gpz_stats_workspace_bytes(F)
+ * bytes.  A serving loop can queue it with a copy of d_minmax to host memory
+ * and learn the relative bound of a request when that copy completes. */
+int gpz_field_range_async(const float *const *h_fields, uint64_t n, uint32_t nfields,
+                          float *d_minmax, void *d_ws, uint64_t ws_bytes, void *stream);
+
 /* For callers that cannot allocate device memory (code that sets up HIP graph
  * captures, tight serving loops, harnesses that forbid hipMalloc):
  * gpz_field_range with no workspace argument and no allocation of any kind.

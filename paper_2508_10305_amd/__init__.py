@@ -25,7 +25,7 @@ EXPORTS = (
     "gpz_decompress_workspace_bytes", "gpz_compress", "gpz_compress_async", "gpz_decompress",
     "gpz_decompress_async", "gpz_compress_f64", "gpz_max_compressed_bytes_f64",
     "gpz_compress_workspace_bytes_f64", "gpz_decompress_f64", "gpz_stats_workspace_bytes", "gpz_bound_check", "gpz_error_stats",
-    "gpz_stream_stats", "gpz_field_range", "gpz_field_range_noalloc", "gpz_rel_to_abs", "gpz_inspect",
+    "gpz_stream_stats", "gpz_field_range", "gpz_field_range_noalloc", "gpz_field_range_async", "gpz_rel_to_abs", "gpz_inspect",
     "gpz_set_timing", "gpz_set_timing_kinds", "gpz_timing_collect", "gpz_strerror",
     "gpz_default_batch_config",
     "gpz_batch_workspace_bytes", "gpz_batch_create", "gpz_batch_rebind", "gpz_batch_compress",
@@ -123,6 +123,8 @@ def _lib():
         L.gpz_stream_stats.restype = ctypes.c_int
         L.gpz_field_range.argtypes = [vp, u64, u32, vp, vp, u64, vp]
         L.gpz_field_range.restype = ctypes.c_int
+        L.gpz_field_range_async.argtypes = [vp, u64, u32, vp, vp, u64, vp]
+        L.gpz_field_range_async.restype = ctypes.c_int
         L.gpz_field_range_noalloc.argtypes = [vp, u64, u32, vp, vp]
         L.gpz_field_range_noalloc.restype = ctypes.c_int
         L.gpz_rel_to_abs.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_float]
@@ -437,6 +439,17 @@ def field_range(fields: Sequence, stream=None, ws=None) -> np.ndarray:
                                 _stream_handle(stream))
     _check(rc, "gpz_field_range")
     return mm.reshape(F, 2)
+
+
+def field_range_async(fields: Sequence, minmax, ws, stream=None):
+    """Queue the field range of `fields` into the float32 CUDA tensor
+    `minmax` (2F values: min, max per field) without synchronizing; `ws`
+    from stats_workspace."""
+    F = len(fields)
+    n = _check_fields(fields)
+    rc = _lib().gpz_field_range_async(ctypes.cast(_ptr_array(fields), ctypes.c_void_p), n, F,
+                                      minmax.data_ptr(), *_ws_args(ws), _stream_handle(stream))
+    _check(rc, "gpz_field_range_async")
 
 
 def field_range_noalloc(fields: Sequence, stream=None) -> np.ndarray:

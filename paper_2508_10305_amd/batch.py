@@ -50,6 +50,34 @@ class _JobArrays:
             J.ws = wss[j].data_ptr() if wss is not None and wss[j] is not None else None
 
 
+class PreparedJob:
+    """One job's C struct and the host arrays it points at, built once (a
+    serving loop builds it when a request is admitted and its bound known)
+    and copied into a job list at launch."""
+
+    __slots__ = ("job", "keep", "blocks")
+
+    def __init__(self, fields, eb, out, dec=None, ws=None, block_size: int = 1024):
+        fl, dl = fields, dec
+        F = len(fl) if fl is not None else len(dl)
+        n = (fl[0] if fl is not None else dl[0]).numel()
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eb, np.float32), (F,)))
+        fa = _ptr_array(fl) if fl is not None else None
+        da = _ptr_array(dl) if dl is not None else None
+        J = Job()
+        J.fields = ctypes.cast(fa, ctypes.c_void_p) if fa is not None else None
+        J.n = n
+        J.nfields = F
+        J.eb = e.ctypes.data_as(ctypes.c_void_p)
+        J.out = out.data_ptr()
+        J.out_capacity = out.numel()
+        J.dec_fields = ctypes.cast(da, ctypes.c_void_p) if da is not None else None
+        J.ws = ws.data_ptr() if ws is not None else None
+        self.job = J
+        self.keep = (e, fa, da)
+        self.blocks = (n + block_size - 1) // block_size
+
+
 class Batch:
     """A bound batch of jobs.  `fields[j]` / `dec[j]` are lists of float32 CUDA
     tensors (either may be None), `outs[j]` uint8 CUDA stream buffers of at
@@ -108,6 +136,19 @@ class Batch:
         self.njobs = arrays.njobs
         self._arrays = arrays
         self.ws = ws
+
+    def rebind_prepared(self, jobs: Sequence[PreparedJob], workspace, stream=None):
+        """Bind prepared jobs: only their structs are copied into one array
+        (the host arrays they point at were built once, with the job)."""
+        arr = (Job * max(1, len(jobs)))()
+        for j, pj in enumerate(jobs):
+            arr[j] = pj.job
+        rc = _lib().gpz_batch_rebind(self.handle, arr, len(jobs), workspace.data_ptr(),
+                                     workspace.numel(), _stream_handle(stream))
+        _check(rc, "gpz_batch_rebind")
+        self.njobs = len(jobs)
+        self._arrays = (arr, list(jobs))
+        self.ws = workspace
 
     def compress(self, stream=None):
         _check(_lib().gpz_batch_compress(self.handle, _stream_handle(stream)), "gpz_batch_compress")

@@ -679,6 +679,21 @@ int gpz_field_range(const float* const* h_fields, uint64_t n, uint32_t nfields, 
     return rc;
 }
 
+int gpz_field_range_async(const float* const* h_fields, uint64_t n, uint32_t nfields,
+                          float* d_minmax, void* d_ws, uint64_t ws_bytes, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nfields < 1 || nfields > kMaxFields || !d_minmax || !d_ws) return GPZ_EINVAL;
+    if (ws_bytes < stats_ws_bytes(nfields)) return GPZ_EINVAL;
+    if (n > 0 && !h_fields) return GPZ_EINVAL;
+    for (uint32_t f = 0; n > 0 && f < nfields; f++)
+        if (!h_fields[f]) return GPZ_EINVAL;
+    int* keys = static_cast<int*>(d_ws);
+    int rc = range_keys_reset(keys, nfields, s);
+    if (rc == GPZ_OK && n > 0) rc = to_status(launch_field_range(h_fields, n, nfields, keys, s));
+    if (rc == GPZ_OK) rc = to_status(launch_range_to_floats(keys, nfields, d_minmax, s));
+    return rc;
+}
+
 int gpz_field_range_noalloc(const float* const* h_fields, uint64_t n, uint32_t nfields,
                             float* h_minmax, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -526,6 +526,33 @@ hipError_t launch_bound_check(const float* const* orig, const float* const* reco
     return hipGetLastError();
 }
 
+namespace {
+
+// The 2F range keys as floats in out[2F] (min, max per field): 0, 0 for a
+// field with no finite value, a zero extreme as +0.0.
+__global__ __launch_bounds__(64) void range_keys_to_floats(const int* __restrict__ keys, uint32_t F,
+                                                           float* __restrict__ out) {
+    for (uint32_t f = threadIdx.x; f < F; f += 64) {
+        const int mn = keys[f], mx = keys[F + f];
+        float lo = 0.0f, hi = 0.0f;
+        if (mn <= mx) {
+            lo = __int_as_float(mn ^ ((mn >> 31) & 0x7FFFFFFF));
+            hi = __int_as_float(mx ^ ((mx >> 31) & 0x7FFFFFFF));
+            if (lo == 0.0f) lo = 0.0f;
+            if (hi == 0.0f) hi = 0.0f;
+        }
+        out[2 * f] = lo;
+        out[2 * f + 1] = hi;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_range_to_floats(const int* keys, uint32_t F, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(range_keys_to_floats, dim3(1), dim3(64), 0, s, keys, F, out);
+    return hipGetLastError();
+}
+
 uint32_t device_cu_count() {
     constexpr int kDevices = 64;
     static std::atomic<int> cached[kDevices];

@@ -303,6 +303,8 @@ hipError_t launch_encode_generic(const EncodeArgs& a, bool deferred_only, hipStr
 hipError_t launch_encode_deferred_then_scan(const EncodeArgs& a, const ScanArgs& sa,
                                             uint32_t* done, hipStream_t s);
 hipError_t launch_decode_generic(const DecodeArgs& a, hipStream_t s);
+// The range keys as floats in device memory (min, max per field).
+hipError_t launch_range_to_floats(const int* keys, uint32_t F, float* out, hipStream_t s);
 // Compute units of the current device (queried once per device, 256 if the
 // query fails).
 uint32_t device_cu_count();

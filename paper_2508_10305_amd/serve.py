@@ -10,8 +10,12 @@ stream can also be served launch-per-request (one plain launch per request)
 for comparison.
 
 Inputs are slices of device-resident pools; decompression requests read
-streams compressed at start-up.  Every result is the same as the request
-processed alone (checked by the tests).
+streams compressed at start-up.  A compression request with a relative
+bound learns it from its own slice: at admission the field range of the
+slice is queued on a range stream with a copy to pinned memory, and the
+request becomes launchable when that copy has landed, so the range is part
+of its latency.  Every result is the same as the request processed alone
+(checked by the tests).
 """
 from __future__ import annotations
 
@@ -22,7 +26,9 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from . import Params, _check, _lib, _ptr_array, _stream_handle, max_compressed_bytes, params
+from . import (Params, _check, _lib, _ptr_array, _stream_handle, field_range_async,
+               max_compressed_bytes, params)
+from .batch import PreparedJob
 
 ALIGN = 256
 
@@ -94,6 +100,7 @@ class Request:
     eb: np.ndarray
     fields: Sequence = ()    # compress: input views; decompress: none
     stream: object = None    # decompress: input stream (uint8 view)
+    rel: float = 0.0         # compress: relative bound (0: eb is absolute and given)
     ws: object = None        # compress: record-slot workspace (reserved at admission)
     # filled by the server
     out_off: int = -1
@@ -104,6 +111,11 @@ class Request:
     batch: int = -1
     nbytes: int = -1         # compress: stream size the library reported
     status: int = -1         # decompress: the decoder's error flag (0: the stream was valid)
+    job: object = None       # the batch job, prepared once its bound is known
+    mm: object = None        # compress with a relative bound: device range (2F floats)
+    range_ws: object = None  # its range workspace
+    mm_row: int = -1         # its pinned host row
+    range_event: object = None
 
 
 @dataclass
@@ -157,6 +169,13 @@ class Server:
             sl.batch_c.capacity_views()
             sl.batch_d.capacity_views()
             self.slots.append(sl)
+        # field ranges of relative-bound requests: their own stream, results
+        # copied to rows of a pinned table
+        self.range_stream = torch.cuda.Stream()
+        self.range_rows = 4096
+        self.h_mm = torch.zeros((self.range_rows, 128), dtype=torch.float32, pin_memory=True)
+        self.free_rows = list(range(self.range_rows))
+        self.stats_ws = int(_lib().gpz_stats_workspace_bytes(64))
         torch.cuda.synchronize()
         self.batches = 0
         self.batch_sizes: List[int] = []
@@ -167,7 +186,8 @@ class Server:
         record-slot workspace of a compression, the output fields of a
         decompression."""
         if r.op == "compress":
-            return _up(max_compressed_bytes(r.n, r.F, self.p)) + self._ws_bytes(r)
+            ranged = _up(8 * r.F) + _up(self.stats_ws) if r.rel else 0
+            return _up(max_compressed_bytes(r.n, r.F, self.p)) + self._ws_bytes(r) + ranged
         return sum(_up(4 * r.n) for _ in range(r.F))
 
     def _ws_bytes(self, r: Request) -> int:
@@ -185,12 +205,38 @@ class Server:
         r.out_off, r.out_bytes, r.t_admit = off, nbytes, now
         if r.op == "compress":
             ob = _up(max_compressed_bytes(r.n, r.F, self.p))
+            wb = self._ws_bytes(r)
             r.out = self.arena.view(off, ob)
-            r.ws = self.arena.view(off + ob, nbytes - ob)
+            r.ws = self.arena.view(off + ob, wb)
+            if r.rel:
+                r.mm = self.arena.view(off + ob + wb, 8 * r.F, torch.float32)
+                r.range_ws = self.arena.view(off + ob + wb + _up(8 * r.F), self.stats_ws)
         else:
             r.out = [self.arena.view(off + f * _up(4 * r.n), 4 * r.n, torch.float32)
                      for f in range(r.F)]
+            r.job = PreparedJob(None, r.eb, r.stream, dec=r.out, block_size=self.B)
         return True
+
+    def _start_range(self, r: Request):
+        """Queue the field range of a relative-bound request's slice and its
+        copy to a pinned row; the request waits for the copy's event."""
+        import torch
+        r.mm_row = self.free_rows.pop()
+        with torch.cuda.stream(self.range_stream):
+            field_range_async(r.fields, r.mm, r.range_ws, stream=self.range_stream)
+            self.h_mm[r.mm_row, : 2 * r.F].copy_(r.mm, non_blocking=True)
+            r.range_event = torch.cuda.Event()
+            r.range_event.record(self.range_stream)
+
+    def _finish_range(self, r: Request):
+        """The slice's absolute bounds (relative bound times its range, in
+        the library), then the request's batch job."""
+        mm = self.h_mm[r.mm_row, : 2 * r.F].numpy()
+        r.eb = np.array([_lib().gpz_rel_to_abs(r.rel, float(mm[2 * f]), float(mm[2 * f + 1]))
+                         for f in range(r.F)], np.float32)
+        self.free_rows.append(r.mm_row)
+        r.mm_row = -1
+        r.job = PreparedJob(r.fields, r.eb, r.out, ws=r.ws, block_size=self.B)
 
     def _release(self, r: Request):
         self.arena.release(r.out_off, r.out_bytes)
@@ -209,12 +255,9 @@ class Server:
             # after a launch that wait would hold the whole loop until the
             # launched batch finished.
             if comp:
-                slot.batch_c.rebind([r.fields for r in comp], [r.eb for r in comp],
-                                    [r.out for r in comp], workspace=ws, stream=slot.stream,
-                                    job_ws=[r.ws for r in comp])
+                slot.batch_c.rebind_prepared([r.job for r in comp], ws, stream=slot.stream)
             if dec:
-                slot.batch_d.rebind(None, [r.eb for r in dec], [r.stream for r in dec],
-                                    dec=[r.out for r in dec], workspace=ws, stream=slot.stream)
+                slot.batch_d.rebind_prepared([r.job for r in dec], ws, stream=slot.stream)
             if comp:
                 slot.batch_c.compress(stream=slot.stream)
                 slot.h_sizes[: len(comp)].copy_(slot.batch_c.capacity_views()[0][: len(comp)],
@@ -293,6 +336,7 @@ class Server:
         max_batch = max_batch or self.max_jobs
         pending = list(requests)
         waiting: List[Request] = []
+        ranging: List[Request] = []
         admitted: List[Request] = []
         done: List[Request] = []
         rejected: List[Request] = []
@@ -335,9 +379,24 @@ class Server:
                 else:
                     waiting.append(r)
                 last_progress = now
-            # admission by the HBM budget, in arrival order
-            while waiting and self._admit(waiting[0], now):
-                admitted.append(waiting.pop(0))
+            # admission by the HBM budget, in arrival order; a relative-bound
+            # compression first learns its bound from its slice
+            while waiting and (not waiting[0].rel or self.free_rows) and \
+                    self._admit(waiting[0], now):
+                r = waiting.pop(0)
+                if r.op == "compress" and r.rel:
+                    self._start_range(r)
+                    ranging.append(r)
+                else:
+                    if r.op == "compress":
+                        r.job = PreparedJob(r.fields, r.eb, r.out, ws=r.ws, block_size=self.B)
+                    admitted.append(r)
+            # ranges complete in order (one stream)
+            while ranging and ranging[0].range_event.query():
+                r = ranging.pop(0)
+                self._finish_range(r)
+                admitted.append(r)
+                last_progress = now
             # launch on free streams
             for slot in self.slots:
                 if not admitted:
@@ -434,7 +493,7 @@ def build_pools(max_n: int, seed: int = 5, kinds=("clusters", "cosmology", "md",
     return pools
 
 
-def template_sizes(n_min: int, n_max: int, count: int = 8) -> List[int]:
+def template_sizes(n_min: int, n_max: int, count: int = 32) -> List[int]:
     return sorted(set(int(round(x)) for x in np.exp(np.linspace(np.log(n_min), np.log(n_max),
                                                                count))))
 
@@ -465,8 +524,8 @@ def make_requests(pools, templates, sizes, count: int, seed: int, rate: float, n
             n = min(r["n"], pool["fields"][0].numel())
             off = int(rng.integers(0, pool["fields"][0].numel() - n + 1))
             reqs.append(Request(i, r["t"], "compress", r["kind"], n, pool["F"],
-                                pool["ebs"][r["rel"]],
-                                fields=[f[off: off + n] for f in pool["fields"]]))
+                                np.zeros(pool["F"], np.float32),
+                                fields=[f[off: off + n] for f in pool["fields"]], rel=r["rel"]))
         else:
             n = min(sizes, key=lambda s: abs(np.log(s) - np.log(r["n"])))
             reqs.append(Request(i, r["t"], "decompress", r["kind"], n, pool["F"],
@@ -475,8 +534,8 @@ def make_requests(pools, templates, sizes, count: int, seed: int, rate: float, n
 
 
 def fresh(reqs: List[Request]) -> List[Request]:
-    return [Request(r.rid, r.t, r.op, r.kind, r.n, r.F, r.eb, fields=r.fields, stream=r.stream)
-            for r in reqs]
+    return [Request(r.rid, r.t, r.op, r.kind, r.n, r.F, r.eb.copy(), fields=r.fields,
+                    stream=r.stream, rel=r.rel) for r in reqs]
 
 
 def bench_main(args, log=print):
@@ -494,6 +553,7 @@ def bench_main(args, log=print):
     templates = build_templates(pools, sizes)
     torch.cuda.synchronize()
     reqs = make_requests(pools, templates, sizes, count, 5, 2000.0, n_min, n_max)
+    log(f"[serve] {count} requests, {len(templates)} decompression templates")
     results = {}
     for label, budget, mode in (("batched", 200 << 30, "batched"),
                                 ("per_request", 200 << 30, "per_request"),
@@ -501,7 +561,8 @@ def bench_main(args, log=print):
                                 ("per_request_overload", 8 << 30, "per_request")):
         # the budget, less 16 GB kept free for the batches' tables and torch
         budget = min(budget, int(torch.cuda.mem_get_info()[0]) - (16 << 30))
-        srv = Server(budget, nstreams=3, max_jobs=64, max_blocks=1 << 20)
+        srv = Server(budget, nstreams=getattr(args, "serve_streams", 3), max_jobs=64,
+                     max_blocks=1 << 20)
         rate_scale = 1.0 if "overload" not in label else 0.1  # 10x arrival rate
         st = srv.run(fresh(reqs), mode=mode, time_scale=rate_scale)
         st["budget_bytes"] = budget
@@ -525,7 +586,8 @@ def bench_main(args, log=print):
         "data": "synthetic",
         "config": {"workload": f"Poisson {count} requests at 2000/s, sizes log-uniform "
                                f"{n_min}-{n_max}, kinds clusters/cosmology/md/lidar, rel eb "
-                               "1e-2/1e-3/1e-4, 50/50 compress/decompress",
+                               "1e-2/1e-3/1e-4 of each compressed slice's own range (its field "
+                               "range inside its latency), 50/50 compress/decompress",
                    "decompress_template_sizes": sizes},
     }
     print(json.dumps(rec), flush=True)

@@ -1,7 +1,8 @@
 """Serving form: continuous batching must give every request exactly the
-result the CPU oracle computes for it alone (stream bytes and size of a
-compression, decoded bits and a clean status of a decompression), and
-admission must respect the HBM budget."""
+result the CPU oracle computes for it alone (the relative bound of a
+compression's own slice, its stream bytes and size; decoded bits and a
+clean status of a decompression), and admission must respect the HBM
+budget."""
 import sys
 
 import numpy as np
@@ -33,7 +34,10 @@ def oracle_result(orc, r):
     (decompress)."""
     if r.op == "compress":
         host = [f.cpu().numpy() for f in r.fields]
-        s, _ = orc.compress(host, r.eb)
+        # the relative bound of the request's own slice, by the oracle
+        eb = orc.rel_ebs(host, r.rel) if r.rel else r.eb
+        assert (eb.view(np.uint32) == r.eb.view(np.uint32)).all(), f"request {r.rid}: bound"
+        s, _ = orc.compress(host, eb)
         return s
     return orc.decompress(r.stream.cpu().numpy(), r.n, r.F)
 
