@@ -94,31 +94,38 @@ struct CompressWs {
     uint64_t bytes;
 };
 
+// Address `off` bytes into the workspace at `base` (nullptr when only the
+// sizes are wanted: integer arithmetic, no pointer offset from null).
+template <typename T>
+T* ws_at(char* base, uint64_t off) {
+    return base ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(base) + off) : nullptr;
+}
+
 // vw: words per value (1 float32, 2 float64)
 CompressWs layout(uint64_t n, uint32_t F, uint32_t B, uint32_t vw, char* base) {
     CompressWs w{};
     const uint64_t nb = nblocks_of(n, B), ns = nsuper_of(nb);
     w.slot_words = (uint32_t)((1 + (uint64_t)F * B * vw + 3) & ~uint64_t(3));
     uint64_t o = 0;
-    w.temp = reinterpret_cast<uint32_t*>(base + o);
+    w.temp = ws_at<uint32_t>(base, o);
     o = align256(o + nb * w.slot_words * 4ull);
     // look-back words, ticket, total, deferred-block count, wide flag and the
     // superblock sums are contiguous: one fill clears what either compaction
     // needs zeroed
-    w.state = reinterpret_cast<uint64_t*>(base + o);
-    w.ticket = reinterpret_cast<uint32_t*>(base + o + nb * 8);
-    w.total = reinterpret_cast<uint64_t*>(base + o + nb * 8 + 8);
-    w.defer_count = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 16);
-    w.wide_flag = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 20);
-    w.done = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 24);
-    w.supsum = reinterpret_cast<uint32_t*>(base + o + nb * 8 + 28);
+    w.state = ws_at<uint64_t>(base, o);
+    w.ticket = ws_at<uint32_t>(base, o + nb * 8);
+    w.total = ws_at<uint64_t>(base, o + nb * 8 + 8);
+    w.defer_count = ws_at<uint32_t>(base, o + nb * 8 + 16);
+    w.wide_flag = ws_at<uint32_t>(base, o + nb * 8 + 20);
+    w.done = ws_at<uint32_t>(base, o + nb * 8 + 24);
+    w.supsum = ws_at<uint32_t>(base, o + nb * 8 + 28);
     w.clear_words = 2 * nb + 7 + ns;
     o = align256(o + nb * 8 + 28 + ns * 4);
-    w.supoff = reinterpret_cast<uint64_t*>(base + o);
+    w.supoff = ws_at<uint64_t>(base, o);
     o = align256(o + ns * 8);
-    w.lens = reinterpret_cast<uint32_t*>(base + o);
+    w.lens = ws_at<uint32_t>(base, o);
     o = align256(o + nb * 4);
-    w.defer = reinterpret_cast<uint32_t*>(base + o);
+    w.defer = ws_at<uint32_t>(base, o);
     o = align256(o + nb * 4);
     w.bytes = o;
     return w;
