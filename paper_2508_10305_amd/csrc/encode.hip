@@ -692,22 +692,19 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         if (lane == 0) start[U] = nb;
     }
     wave_lds_sync();
-    // delta coding of the distinct IDs (stored as delta - 1) and counts - 1:
-    // widths now, values again when they are packed
-    uint32_t w_gap, w_cnt;
-    {
-        uint32_t g[ITEMS], c[ITEMS];
-        run_gaps<ITEMS>(uniq, U, lane, g);
-        run_counts<ITEMS>(start, U, lane, c);
-        uint32_t gmax = 0, cmax = 0;
+    // delta coding of the distinct IDs (stored as delta - 1) and counts - 1,
+    // kept in registers until they are packed
+    uint32_t gv[ITEMS], cv[ITEMS];
+    run_gaps<ITEMS>(uniq, U, lane, gv);
+    run_counts<ITEMS>(start, U, lane, cv);
+    uint32_t gmax = 0, cmax = 0;
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            gmax = max(gmax, g[j]);
-            cmax = max(cmax, c[j]);
-        }
-        w_gap = bit_width(wave_max_u32(gmax));
-        w_cnt = bit_width(wave_max_u32(cmax));
+    for (int j = 0; j < ITEMS; j++) {
+        gmax = max(gmax, gv[j]);
+        cmax = max(cmax, cv[j]);
     }
+    const uint32_t w_gap = bit_width(wave_max_u32(gmax));
+    const uint32_t w_cnt = bit_width(wave_max_u32(cmax));
     if (lane == 0) {
         rec[0] = U << 2;
         rec[1] = w_gap | (w_cnt << 5) | (sk[0] << 10) | (sk[1] << 15) | (sk[2] << 20);
@@ -716,21 +713,19 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     // ---- arrays in record order: gaps, counts, then one section per field
     uint32_t pos = 2;
     bool over = wide;  // (single pass only: such a block is stored raw)
-    for (uint32_t arr = 0; arr < 2 + F; arr++) {
+    const uint32_t gw = words_for(U, w_gap), cw = words_for(U, w_cnt);
+    if (pos + gw + cw > cap) {
+        over = true;
+    } else {
+        wave_lds_sync();  // uniq/start reads done before `work` is reused
+        pack_array<ITEMS>(gv, U, w_gap, rec + pos, kvbuf, lane);
+        pack_array<ITEMS>(cv, U, w_cnt, rec + pos + gw, kvbuf, lane);
+        pos += gw + cw;
+    }
+    for (uint32_t f = 0; f < F && !over; f++) {
         uint32_t vals[ITEMS];
         uint32_t w, count, nout = 0;
-        const uint32_t f = arr - 2;
-        if (arr < 2) {
-            count = U;
-            w = arr == 0 ? w_gap : w_cnt;
-            if (arr == 0) run_gaps<ITEMS>(uniq, U, lane, vals);
-            else run_counts<ITEMS>(start, U, lane, vals);
-            if (pos + words_for(count, w) > cap) {
-                over = true;
-                break;
-            }
-            wave_lds_sync();  // uniq/start reads done before `work` is reused
-        } else {
+        {
             FieldCodes c{0.0f, 0u, true};
             uint32_t width = 24, vmax = 0, no = 0;
             bool key = false;
