@@ -257,12 +257,11 @@ __device__ __forceinline__ void pack16(const uint32_t (&v)[16], uint32_t* dst, u
 #define GPZ_PACK16_CASE(W) \
     case W: pack16<W>(v, first, lane); break;
 
-// Fixed-length packing of one array into dst (Sec. 4.3), staged in LDS and
-// copied out with coalesced stores.
+// Fixed-length packing of one array (Sec. 4.3) into the LDS staging buffer:
+// value i of `count` values of width w goes to bits [i*w, i*w+w) of it.
 template <int ITEMS>
-__device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t count, uint32_t w,
-                                           uint32_t* __restrict__ dst, uint32_t* stage,
-                                           uint32_t lane) {
+__device__ __forceinline__ void pack_stage(const uint32_t (&v)[ITEMS], uint32_t count, uint32_t w,
+                                           uint32_t* stage, uint32_t lane) {
     const uint32_t nwords = words_for(count, w);
     if (nwords == 0) return;
     if constexpr (ITEMS == 16) {
@@ -279,13 +278,18 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
     } else {
         pack_generic<ITEMS>(v, nwords, count, w, stage, lane);
     }
-    wave_lds_sync();
-    // Copy out four words per lane at a time: the four staging reads are all
-    // issued before the stores, so they cost one LDS round trip, not four.
-    // Whole 256-word steps store unconditionally, at 32-bit byte offsets from
-    // the array's scalar base; only the last, partial step is predicated.
-    // Reads past nwords stay inside the staging buffer (its size is checked
-    // against the largest array, B values of 24 bits) and are never stored.
+}
+
+// The nwords staged words to dst with coalesced stores, four words per lane
+// at a time: the four staging reads are all issued before the stores, so
+// they cost one LDS round trip, not four.  Whole 256-word steps store
+// unconditionally, at 32-bit byte offsets from the array's scalar base; only
+// the last, partial step is predicated.  Reads past nwords stay inside the
+// staging buffer (its size is checked against the largest array, B values
+// of 24 bits) and are never stored.
+template <int ITEMS>
+__device__ __forceinline__ void copy_out(uint32_t nwords, uint32_t* __restrict__ dst,
+                                         const uint32_t* stage, uint32_t lane) {
     uint8_t* const base = reinterpret_cast<uint8_t*>(dst);
     const uint32_t whole = nwords & ~255u;
     for (uint32_t i0 = 0; i0 < whole; i0 += 256) {
@@ -307,6 +311,19 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
             if (whole + 64 * u + lane < nwords)
                 *reinterpret_cast<uint32_t*>(base + 4u * (whole + 64u * u + lane)) = t[u];
     }
+}
+
+// Fixed-length packing of one array into dst (Sec. 4.3), staged in LDS and
+// copied out with coalesced stores.
+template <int ITEMS>
+__device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t count, uint32_t w,
+                                           uint32_t* __restrict__ dst, uint32_t* stage,
+                                           uint32_t lane) {
+    const uint32_t nwords = words_for(count, w);
+    if (nwords == 0) return;
+    pack_stage<ITEMS>(v, count, w, stage, lane);
+    wave_lds_sync();
+    copy_out<ITEMS>(nwords, dst, stage, lane);
     wave_lds_sync();
 }
 
@@ -714,12 +731,19 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     uint32_t pos = 2;
     bool over = wide;  // (single pass only: such a block is stored raw)
     const uint32_t gw = words_for(U, w_gap), cw = words_for(U, w_cnt);
+    // Each array's packed words leave the staging buffer while the next
+    // field's permutation reads are in flight (one LDS round trip for both):
+    // `pend` words staged for `pend_dst` are still to be copied out.
+    uint32_t pend = 0;
+    uint32_t* pend_dst = rec;
     if (pos + gw + cw > cap) {
         over = true;
     } else {
         wave_lds_sync();  // uniq/start reads done before `work` is reused
         pack_array<ITEMS>(gv, U, w_gap, rec + pos, kvbuf, lane);
-        pack_array<ITEMS>(cv, U, w_cnt, rec + pos + gw, kvbuf, lane);
+        pack_stage<ITEMS>(cv, U, w_cnt, kvbuf, lane);
+        pend = cw;
+        pend_dst = rec + pos + gw;
         pos += gw + cw;
     }
     for (uint32_t f = 0; f < F && !over; f++) {
@@ -791,8 +815,15 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
                                                       width)
                               : 0u;
         }
-        pack_array<ITEMS>(vals, count, w, rec + pos, kvbuf, lane);
-        pos += words_for(count, w);
+        if (pend) {
+            wave_lds_sync();
+            copy_out<ITEMS>(pend, pend_dst, kvbuf, lane);
+        }
+        wave_lds_sync();  // the staged words are read before they are replaced
+        pack_stage<ITEMS>(vals, count, w, kvbuf, lane);
+        pend = words_for(count, w);
+        pend_dst = rec + pos;
+        pos += pend;
         if (nout) {
             // outlier flags of the sorted positions, read again from the staging
             uint32_t flags = 0;
@@ -816,6 +847,11 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             pos += 2 * nout;
         }
         wave_lds_sync();  // staging reads done before the next field overwrites it
+    }
+    if (!over && pend) {
+        wave_lds_sync();
+        copy_out<ITEMS>(pend, pend_dst, kvbuf, lane);
+        wave_lds_sync();
     }
 
     if (!SINGLE && wide) {
