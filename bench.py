@@ -253,6 +253,8 @@ def main():
                     help="plain per-snapshot launch (default), batched snapshots, serving loop, "
                          "a plain device copy of the snapshot's bytes (HBM reference), or a "
                          "rate-distortion sweep over the synthetic workloads")
+    ap.add_argument("--rd-drawn-only", action="store_true",
+                    help="rate-distortion form: drawn storage order only")
     ap.add_argument("--batch-grid", type=int, default=0,
                     help="batched form: persistent grid, 0 = one workgroup per block (with "
                          "--batch-tile, skips the autotuner)")
@@ -541,13 +543,21 @@ def bench_rd(args):
 
     import paper_2508_10305_amd as gpz
     from paper_2508_10305_amd import synth
-    workloads = (("cosmology", 64_000_000), ("md", 32_000_000), ("lidar", 100_000_000),
-                 ("clusters", 1_000_000))
+    # drawn storage order (primary), then the other order of each workload
+    # (file-like locality; for md, whose drawn order is the lattice order, a
+    # shuffle), for compression ratio
+    workloads = (("cosmology", 64_000_000, "drawn"), ("md", 32_000_000, "drawn"),
+                 ("lidar", 100_000_000, "drawn"), ("clusters", 1_000_000, "drawn"),
+                 ("cosmology", 64_000_000, "local"), ("md", 32_000_000, "shuffled"),
+                 ("lidar", 100_000_000, "local"), ("clusters", 1_000_000, "local"))
+    if args.rd_drawn_only:
+        workloads = tuple(w for w in workloads if w[2] == "drawn")
     rels = (1e-2, 1e-3, 1e-4, 1e-5)
     rows = []
-    for kind, n in workloads:
+    for kind, n, order in workloads:
         t0 = time.time()
-        host = synth.make(kind, n, {"clusters": 0, "cosmology": 1, "md": 2, "lidar": 3}[kind])
+        host = synth.make(kind, n, {"clusters": 0, "cosmology": 1, "md": 2, "lidar": 3}[kind],
+                          order=order)
         fields = [torch.from_numpy(f).cuda() for f in host]
         del host
         n, F = fields[0].numel(), len(fields)
@@ -577,7 +587,7 @@ def bench_rd(args):
             e[2].record()
             torch.cuda.synchronize()
             tc, td = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
-            row = {"workload": kind, "n": n, "fields": F, "rel_eb": rel,
+            row = {"workload": kind, "order": order, "n": n, "fields": F, "rel_eb": rel,
                    "compression_ratio": round(S / C, 3),
                    "bit_rate_bits_per_value": round(8 * C / (n * F), 4),
                    "aggregate_psnr_db": round(st["psnr"], 3),
@@ -586,7 +596,7 @@ def bench_rd(args):
                    "compress_GBps": round(S / (tc * 1e-3) / 1e9, 1),
                    "decompress_GBps": round(S / (td * 1e-3) / 1e9, 1)}
             rows.append(row)
-            log(f"[rd] {kind} rel {rel:g}: CR {row['compression_ratio']} "
+            log(f"[rd] {kind} ({order}) rel {rel:g}: CR {row['compression_ratio']} "
                 f"{row['bit_rate_bits_per_value']} bits/value PSNR {row['aggregate_psnr_db']} dB")
         del comp, fields, outs
         torch.cuda.empty_cache()

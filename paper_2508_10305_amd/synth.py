@@ -60,12 +60,15 @@ def _streams(seed: int, count: int):
 
 
 def clusters(n: int = 1_000_000, seed: int = 0, n_clusters: int = 64, sigma: float = 0.01,
-             background: float = 0.2, extra_fields: int = 0) -> List[np.ndarray]:
+             background: float = 0.2, extra_fields: int = 0, labels: np.ndarray | None = None
+             ) -> List[np.ndarray]:
     """Positions in [0,1)^3: a mixture of ``n_clusters`` isotropic Gaussians
     (equal weights, centres uniform in the cube) plus a ``background``
     fraction of uniform points; coordinates wrap periodically.  Particles
     appear in draw order (labels i.i.d. per particle).  ``extra_fields``
-    standard-normal attribute fields follow x, y, z."""
+    standard-normal attribute fields follow x, y, z.  ``labels`` (n int32,
+    optional) receives each particle's cluster, ``n_clusters`` for the
+    background."""
     nch = (n + CHUNK - 1) // CHUNK
     rs = _streams(seed, nch)
     centres = rs[0].random((n_clusters, 3))
@@ -75,6 +78,8 @@ def clusters(n: int = 1_000_000, seed: int = 0, n_clusters: int = 64, sigma: flo
         r = rs[ci + 1]
         lab = r.integers(0, n_clusters, m)
         bg = r.random(m) < background
+        if labels is not None:
+            labels[s:s + m] = np.where(bg, n_clusters, lab)
         p = centres[lab] + sigma * r.standard_normal((m, 3))
         p[bg] = r.random((int(bg.sum()), 3))
         p = np.mod(p, 1.0)
@@ -89,11 +94,14 @@ def clusters(n: int = 1_000_000, seed: int = 0, n_clusters: int = 64, sigma: flo
 
 
 def cosmology(n: int = 64_000_000, seed: int = 1, box: float = 256.0, n_halos: int = 4096,
-              background: float = 0.3, vsig: float = 300.0) -> List[np.ndarray]:
+              background: float = 0.3, vsig: float = 300.0, labels: np.ndarray | None = None
+              ) -> List[np.ndarray]:
     """x, y, z, vx, vy, vz of a HACC-like snapshot: halo centres uniform in a
     periodic box, halo widths log-uniform in [0.1, 2], 30 % uniform
     background; velocities = per-halo bulk velocity ~ N(0, vsig^2) per axis
-    (zero for the background) plus N(0, vsig^2) dispersion."""
+    (zero for the background) plus N(0, vsig^2) dispersion.  ``labels`` (n
+    int32, optional) receives each particle's halo, ``n_halos`` for the
+    background."""
     nch = (n + CHUNK - 1) // CHUNK
     rs = _streams(seed, nch)
     cen = rs[0].random((n_halos, 3)) * box
@@ -105,6 +113,8 @@ def cosmology(n: int = 64_000_000, seed: int = 1, box: float = 256.0, n_halos: i
         r = rs[ci + 1]
         lab = r.integers(0, n_halos, m)
         bg = r.random(m) < background
+        if labels is not None:
+            labels[s:s + m] = np.where(bg, n_halos, lab)
         p = cen[lab] + sig[lab, None] * r.standard_normal((m, 3))
         p[bg] = r.random((int(bg.sum()), 3)) * box
         p = np.mod(p, box)
@@ -215,17 +225,51 @@ def request_stream(count: int = 20_000, seed: int = 5, rate: float = 2000.0, n_m
 KINDS = ("clusters", "cosmology", "md", "lidar")
 
 
-def make(kind: str, n: int, seed: int) -> List[np.ndarray]:
-    """A particle set of ``kind`` with about ``n`` particles."""
+def make(kind: str, n: int, seed: int, order: str = "drawn") -> List[np.ndarray]:
+    """A particle set of ``kind`` with about ``n`` particles, in the order the
+    generator draws it (``order="drawn"``), in the file-like order of
+    ``local_order`` (``order="local"``; for md the drawn lattice order is
+    already local), or seeded-shuffled (``order="shuffled"``)."""
+    labels = np.empty(n, np.int32) if order == "local" and kind in ("clusters", "cosmology") \
+        else None
     if kind == "clusters":
-        return clusters(n, seed)
-    if kind == "cosmology":
-        return cosmology(n, seed, n_halos=max(16, min(4096, n // 16_000)))
-    if kind == "md":
+        out = clusters(n, seed, labels=labels)
+    elif kind == "cosmology":
+        out = cosmology(n, seed, n_halos=max(16, min(4096, n // 16_000)), labels=labels)
+    elif kind == "md":
         cells = max(1, int(np.ceil((n / 4) ** (1 / 3))))
-        return md(cells, seed, n=n)
+        out = md(cells, seed, n=n)
+    elif kind == "lidar":
+        out = lidar(n, seed)
+    else:
+        raise ValueError(kind)
+    if order == "drawn" or (order == "local" and kind == "md"):
+        return out
+    if order == "shuffled":
+        perm = np.random.Generator(np.random.PCG64(seed + 7)).permutation(out[0].size)
+    elif order == "local":
+        perm = local_order(kind, out, labels)
+    else:
+        raise ValueError(order)
+    return [f[perm] for f in out]
+
+
+def local_order(kind: str, fields: List[np.ndarray], labels: np.ndarray | None = None
+                ) -> np.ndarray:
+    """Permutation to a file-like storage order, the particles stored near
+    their spatial neighbours as the paper's blocks assume of real files:
+    clusters and cosmology cluster- (halo-) major with the background last,
+    each group in draw order; LiDAR in 10-unit strips of y, serpentine in x
+    (as a scanner sweeps)."""
+    if kind in ("clusters", "cosmology"):
+        if labels is None:
+            raise ValueError("labels required")
+        return np.argsort(labels, kind="stable")
     if kind == "lidar":
-        return lidar(n, seed)
+        x, y = fields[0], fields[1]
+        strip = np.floor(y.astype(np.float64) / 10.0).astype(np.int64)
+        xk = np.where(strip % 2 == 0, x, -x)
+        return np.lexsort((xk, strip))
     raise ValueError(kind)
 
 
