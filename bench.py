@@ -174,15 +174,40 @@ def batched_figures(gpz, torch, steps):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
     ms_plain = timed(plain_round, 3)
+    # the same plain calls captured once in a HIP graph and replayed: the
+    # plain form's kernels without the host's launch gaps, the per-byte
+    # rate the batched form is compared with
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plain_round()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        plain_round()
+    ms_plain_graph = timed(graph.replay, 3)
     ref = []
     for j, sp in enumerate(specs):
         s_, _ = comps[j].compress(fields[j], ebs[j])
         ref.append(s_.clone())
-    del comps
+    # every replayed stream is the one the eager call writes
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_same = all(int(comps[j].nbytes_dev.item()) == ref[j].numel() and
+                     bool(torch.equal(comps[j].out[: ref[j].numel()], ref[j]))
+                     for j in range(len(specs)))
+    del graph, comps
     ws = torch.empty(Batch.workspace_bytes(fields, ebs, outs, decs, p), dtype=torch.uint8,
                      device="cuda")
+    # launch shape: the autotuner's cached pick for this device and batch
+    # shape, else one workgroup per block (its pick on MI355X)
+    from paper_2508_10305_amd import autotune
+    total_blocks = sum((sp["n"] + 1023) // 1024 for sp in specs)
+    key = autotune.shape_key(torch.cuda.get_device_name(0), 1024, total_blocks, len(specs))
+    pick = autotune.load_cache().get(key, {"grid": 0, "tile": 1})
     cfg = default_config()
-    cfg.grid, cfg.tile, cfg.use_graph = 0, 1, 1  # the autotuner's pick on MI355X
+    cfg.grid, cfg.tile, cfg.use_graph = pick["grid"], pick["tile"], 1
     b = Batch(fields, ebs, outs, dec=decs, p=p, config=cfg, workspace=ws)
 
     def rnd():
@@ -199,7 +224,12 @@ def batched_figures(gpz, torch, steps):
            "GBps": round(2 * S / (ms * 1e-3) / 1e9, 1),
            "roofline_frac": round(2 * (S + C) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
            "plain_loop_ms": round(ms_plain, 4), "speedup_vs_plain_loop": round(ms_plain / ms, 3),
-           "streams_identical_to_plain": same, "launch": {"grid": 0, "tile": 1, "graph": 1}}
+           "plain_graph_ms": round(ms_plain_graph, 4),
+           "per_byte_vs_plain_graph": round(ms_plain_graph / ms, 3),
+           "plain_graph_streams_identical": graph_same,
+           "streams_identical_to_plain": same,
+           "launch": {"grid": pick["grid"], "tile": pick["tile"], "graph": 1,
+                      "cached_pick": key in autotune.load_cache()}}
     del fields, outs, decs, ws, ref
     torch.cuda.empty_cache()
     return out
@@ -788,7 +818,8 @@ def bench_batched(args):
         "speedup_vs_plain_loop": round(ms_plain / ms_batch, 3),
         "streams_identical_to_plain": same,
         "compression_ratio": round(S / C, 4),
-        "autotune": {"grid": tuned["grid"], "tile": tuned["tile"], "table": tuned["table"]},
+        "autotune": {"key": key, "grid": tuned["grid"], "tile": tuned["tile"],
+                     "ms": tuned.get("ms"), "table": tuned["table"]},
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{len(specs)} snapshots, particles log-uniform 10K-8M, 3-6 float32 "

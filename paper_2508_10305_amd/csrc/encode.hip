@@ -901,16 +901,16 @@ struct EncodeSmem {
 };
 
 // Three-step compaction: one workgroup per block, block index = workgroup
-// index.  Full blocks and the partial last block run in separate kernels so
-// that the full-block code carries no bounds checks.
-template <int ITEMS, bool FULL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_blocks(EncodeArgs a, uint32_t first_block) {
+// index.  Full blocks take the path without bounds checks, the partial last
+// block (if any) the checked one.
+template <int ITEMS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_blocks(EncodeArgs a) {
     constexpr uint32_t B = 64 * ITEMS;
     __shared__ EncodeSmem<ITEMS> sm;
-    const uint32_t b = first_block + blockIdx.x;
-    const uint64_t base = (uint64_t)b * B;
-    const uint32_t nb = (uint32_t)((a.n - base) < B ? (a.n - base) : B);
-    encode_block<ITEMS, FULL, false>(a, b, nb, sm.kvbuf, sm.work);
+    const uint32_t b = blockIdx.x;
+    const uint64_t left = a.n - (uint64_t)b * B;
+    if (left >= B) encode_block<ITEMS, true, false>(a, b, B, sm.kvbuf, sm.work);
+    else encode_block<ITEMS, false, false>(a, b, (uint32_t)left, sm.kvbuf, sm.work);
 }
 
 // Single-pass compaction: blocks are numbered by a ticket taken when the
@@ -939,11 +939,10 @@ void launch_encode_items(const EncodeArgs& a, bool single_pass, hipStream_t s) {
         else hipLaunchKernelGGL(empty_stream, dim3(1), dim3(64), 0, s, a);
         return;
     }
-    // every block but a partial last one runs the bounds-check-free kernel
-    const uint32_t nfull = (uint32_t)(a.n / (64 * ITEMS));
-    if (nfull) hipLaunchKernelGGL((encode_blocks<ITEMS, true>), dim3(nfull), dim3(64), 0, s, a, 0u);
-    if (nfull < a.nblocks)
-        hipLaunchKernelGGL((encode_blocks<ITEMS, false>), dim3(1), dim3(64), 0, s, a, nfull);
+    // one launch: full blocks take the path without bounds checks, a partial
+    // last block the checked one, alongside them (not in a second launch
+    // that would wait for the first)
+    if (a.nblocks) hipLaunchKernelGGL(encode_blocks<ITEMS>, dim3(a.nblocks), dim3(64), 0, s, a);
 }
 
 // Persistent encoder over the full blocks of many snapshots: each wave takes
