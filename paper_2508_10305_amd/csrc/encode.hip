@@ -332,7 +332,7 @@ __device__ __forceinline__ void pack_array(const uint32_t (&v)[ITEMS], uint32_t 
 // its private counter column give the within-lane rank), a raking scan in
 // (digit, lane) order gives every (digit, lane) its first slot, and items are
 // scattered to their slots and read back blocked.
-template <int ITEMS, bool FULL>
+template <int ITEMS, bool FULL, bool LEAN = false>
 __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, uint32_t nb,
                                            uint32_t lane, uint32_t* cnt, uint32_t* kvbuf) {
     uint4* c4 = reinterpret_cast<uint4*>(cnt);
@@ -347,7 +347,43 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
         else rank[j] = 0u;
     }
     wave_lds_sync();
-    {
+    if constexpr (LEAN) {
+        // as below, in two halves of 16 counters (the counters are read
+        // twice), and the digits extracted again after the scan: fewer
+        // registers held across it
+        uint4* row = reinterpret_cast<uint4*>(cnt + (lane >> 1) * kRow + (lane & 1) * 32);
+        uint32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint4 t = row[k];
+            run += t.x + t.y + t.z + t.w;
+        }
+        uint32_t before = wave_incl_scan_u32(run) - run;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            uint32_t c[16];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint4 t = row[4 * h + k];
+                c[4 * k + 0] = t.x;
+                c[4 * k + 1] = t.y;
+                c[4 * k + 2] = t.z;
+                c[4 * k + 3] = t.w;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                const uint32_t t = c[k];
+                c[k] = before;
+                before += t;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                row[4 * h + k] = make_uint4(c[4 * k], c[4 * k + 1], c[4 * k + 2], c[4 * k + 3]);
+            wave_lds_sync();
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) asm volatile("" : "+v"(kv[j]));
+    } else {
         // lane r scans flat entries [32r, 32r+32) of (digit, lane) order:
         // digit r/2, lanes 32*(r%2) .. 32*(r%2)+31, contiguous in its row
         uint4* row = reinterpret_cast<uint4*>(cnt + (lane >> 1) * kRow + (lane & 1) * 32);
@@ -592,7 +628,10 @@ __device__ __forceinline__ void defer_block(const EncodeArgs& a, uint32_t b, uin
     if (lane == 0) a.defer[atomicAdd(a.defer_count, 1u)] = b;
 }
 
-template <int ITEMS, bool FULL, bool SINGLE>
+// EARLY: how many fields after the key fields are loaded and quantized with
+// them, before the sort (at most three); the others are loaded and quantized
+// in the field loop.  With none, fewer values are held across the sort.
+template <int ITEMS, bool FULL, bool SINGLE, int EARLY = 3>
 __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, uint32_t nb,
                                              uint32_t* kvbuf, uint32_t* work) {
     constexpr uint32_t B = 64 * ITEMS;
@@ -612,7 +651,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     for (int ax = 0; ax < 3; ax++)
         if ((uint32_t)ax < KF) load_block<ITEMS, FULL>(a.x[ax], base, nb, lane, xk[ax]);
 #pragma unroll
-    for (int e = 0; e < 3; e++)
+    for (int e = 0; e < EARLY; e++)
         if (KF + e < F) load_block<ITEMS, FULL>(a.x[KF + e], base, nb, lane, xo[e]);
     // codes are 2*q + outlier (Sec. 4.1)
     uint32_t qk[3][ITEMS];
@@ -638,7 +677,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 #pragma unroll
     for (int e = 0; e < 3; e++) {
         co[e] = {0.0f, 0u, true};
-        if (KF + e < F) {
+        if (e < EARLY && KF + e < F) {
             const uint32_t f = KF + e;
             co[e] = quantize_field<ITEMS, FULL>(xo[e], nb, lane, a.inv[f], a.twoeb[f], a.eb[f],
                                                 qo[e]);
@@ -676,7 +715,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     const uint32_t keybits = K * KF;
     for (uint32_t sh = 0; sh < keybits; sh += kDigitBits) {
         if (((keyor >> sh) & (kDigits - 1)) == 0) continue;  // identity pass
-        radix_pass<ITEMS, FULL>(kv, sh, nb, lane, work, kvbuf);
+        radix_pass<ITEMS, FULL, EARLY == 0>(kv, sh, nb, lane, work, kvbuf);
     }
 
     // ---- Stage 3 (Sec. 4.3): run-length coding of the sorted IDs
@@ -747,6 +786,12 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         pos += gw + cw;
     }
     for (uint32_t f = 0; f < F && !over; f++) {
+        if constexpr (EARLY == 0) {
+            // the permutation's LDS offsets are recomputed per field instead
+            // of being held in registers across the loop
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) asm volatile("" : "+v"(kv[j]));
+        }
         uint32_t vals[ITEMS];
         uint32_t w, count, nout = 0;
         {
@@ -762,7 +807,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             // offset for a key field (its low sk bits), the whole code
             // otherwise.
             uint4* mine = reinterpret_cast<uint4*>(work + lane * (ITEMS + 4));
-            const uint32_t src = f < KF ? f : 3 + (f - KF);
+            const uint32_t src = f < KF ? f : (f - KF < (uint32_t)EARLY ? 3 + (f - KF) : 6u);
             switch (src) {
 #define GPZ_STAGE(N, QA, C, KEY, WIDTH)                                  \
     case N:                                                              \
@@ -913,6 +958,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
     else encode_block<ITEMS, false, false>(a, b, (uint32_t)left, sm.kvbuf, sm.work);
 }
 
+// The same with no early fields beside the key fields (EARLY = 0) and the
+// sort's lean scan: at most 168 VGPRs, three waves per SIMD instead of two.
+// At B = 1024 this is faster on every workload measured (cosmology 64M x 6
+// -4 %, md 32M x 6 -4 %, LiDAR 100M x 3 -13 %): the late fields' loads are
+// hidden by the third wave.
+template <int ITEMS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void encode_blocks_lean(EncodeArgs a) {
+    constexpr uint32_t B = 64 * ITEMS;
+    __shared__ EncodeSmem<ITEMS> sm;
+    const uint32_t b = blockIdx.x;
+    const uint64_t left = a.n - (uint64_t)b * B;
+    if (left >= B) encode_block<ITEMS, true, false, 0>(a, b, B, sm.kvbuf, sm.work);
+    else encode_block<ITEMS, false, false, 0>(a, b, (uint32_t)left, sm.kvbuf, sm.work);
+}
+
 // Single-pass compaction: blocks are numbered by a ticket taken when the
 // workgroup starts, so a block only ever waits on blocks already running.
 template <int ITEMS>
@@ -942,7 +1002,11 @@ void launch_encode_items(const EncodeArgs& a, bool single_pass, hipStream_t s) {
     // one launch: full blocks take the path without bounds checks, a partial
     // last block the checked one, alongside them (not in a second launch
     // that would wait for the first)
-    if (a.nblocks) hipLaunchKernelGGL(encode_blocks<ITEMS>, dim3(a.nblocks), dim3(64), 0, s, a);
+    if (a.nblocks == 0) return;
+    if constexpr (ITEMS == 16)
+        hipLaunchKernelGGL(encode_blocks_lean<ITEMS>, dim3(a.nblocks), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL(encode_blocks<ITEMS>, dim3(a.nblocks), dim3(64), 0, s, a);
 }
 
 // Persistent encoder over the full blocks of many snapshots: each wave takes
@@ -973,7 +1037,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
 // around the block, so the compiler keeps the register budget of the plain
 // kernel.
 template <int ITEMS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_batch_direct(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ITEMS == 16 ? 3 : 2))) void encode_batch_direct(
     const EncodeArgs* __restrict__ jobs, const BatchLaunch* __restrict__ L) {
     constexpr uint32_t B = 64 * ITEMS;
     __shared__ EncodeSmem<ITEMS> sm;
@@ -981,12 +1045,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
     if (g >= L->total_full) return;
     const uint32_t* prefix = L->full_prefix;
     const uint32_t j = find_job(prefix, L->njobs, g);
-    encode_block<ITEMS, true, false>(jobs[j], g - prefix[j], B, sm.kvbuf, sm.work);
+    encode_block<ITEMS, true, false, ITEMS == 16 ? 0 : 3>(jobs[j], g - prefix[j], B, sm.kvbuf, sm.work);
 }
 
 // The partial last block of each snapshot that has one.
 template <int ITEMS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void encode_batch_tails(const EncodeArgs* __restrict__ jobs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ITEMS == 16 ? 3 : 2))) void encode_batch_tails(const EncodeArgs* __restrict__ jobs,
                                                          const BatchLaunch* __restrict__ L) {
     constexpr uint32_t B = 64 * ITEMS;
     __shared__ EncodeSmem<ITEMS> sm;
@@ -995,7 +1059,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
         const EncodeArgs& a = jobs[__builtin_amdgcn_readfirstlane((int)L->tail_jobs[t])];
         const uint32_t b = a.nblocks - 1;
         const uint32_t nb = (uint32_t)(a.n - (uint64_t)b * B);
-        encode_block<ITEMS, false, false>(a, b, nb, sm.kvbuf, sm.work);
+        encode_block<ITEMS, false, false, ITEMS == 16 ? 0 : 3>(a, b, nb, sm.kvbuf, sm.work);
         __syncthreads();
     }
 }
