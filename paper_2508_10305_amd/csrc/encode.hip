@@ -628,12 +628,35 @@ __device__ __forceinline__ void defer_block(const EncodeArgs& a, uint32_t b, uin
     if (lane == 0) a.defer[atomicAdd(a.defer_count, 1u)] = b;
 }
 
+// The block's LDS: one region whose phases reuse it.
+//  - sort: radix counters (kCounterWords, 68-word digit rows) and, aliased
+//    with them, the scatter target in the padded blocked layout (64*(ITEMS+4)
+//    words): each pass reads every counter it needs before its first
+//    scatter store, and a wave's LDS operations execute in issue order;
+//  - run tables: uniq[0, B), start[0, B] at B, per-lane scratch words for
+//    the branch-free run stores at 2B + 64 and 2B + 128;
+//  - field loop: the field's codes in the padded blocked layout at 0, and
+//    the packer's staging from kStageAt (read in steps of 256 words; the
+//    widest array, B values of 24 bits, stays inside).
+template <int ITEMS>
+struct EncodeSmem {
+    static constexpr uint32_t B = 64 * ITEMS;
+    static constexpr uint32_t kStageAt = 64 * (ITEMS + 4);
+    static constexpr uint32_t kStageWords = (48 * ITEMS + 255) / 256 * 256;
+    static constexpr uint32_t kA = kCounterWords > 2 * B + 192 ? kCounterWords : 2 * B + 192;
+    static constexpr uint32_t kWords =
+        kA > kStageAt + kStageWords ? kA : kStageAt + kStageWords;
+    static_assert(64 * (ITEMS + 4) <= kWords, "scatter target inside the region");
+    __align__(16) uint32_t buf[kWords];
+};
+
 // EARLY: how many fields after the key fields are loaded and quantized with
 // them, before the sort (at most three); the others are loaded and quantized
 // in the field loop.  With none, fewer values are held across the sort.
 template <int ITEMS, bool FULL, bool SINGLE, int EARLY = 3>
 __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, uint32_t nb,
-                                             uint32_t* kvbuf, uint32_t* work) {
+                                             uint32_t* work) {
+    uint32_t* const stage = work + EncodeSmem<ITEMS>::kStageAt;
     constexpr uint32_t B = 64 * ITEMS;
     const uint32_t lane = threadIdx.x;
     const uint64_t base = (uint64_t)b * B;
@@ -715,7 +738,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     const uint32_t keybits = K * KF;
     for (uint32_t sh = 0; sh < keybits; sh += kDigitBits) {
         if (((keyor >> sh) & (kDigits - 1)) == 0) continue;  // identity pass
-        radix_pass<ITEMS, FULL, EARLY == 0>(kv, sh, nb, lane, work, kvbuf);
+        radix_pass<ITEMS, FULL, EARLY == 0>(kv, sh, nb, lane, work, work);
     }
 
     // ---- Stage 3 (Sec. 4.3): run-length coding of the sorted IDs
@@ -779,8 +802,8 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         over = true;
     } else {
         wave_lds_sync();  // uniq/start reads done before `work` is reused
-        pack_array<ITEMS>(gv, U, w_gap, rec + pos, kvbuf, lane);
-        pack_stage<ITEMS>(cv, U, w_cnt, kvbuf, lane);
+        pack_array<ITEMS>(gv, U, w_gap, rec + pos, stage, lane);
+        pack_stage<ITEMS>(cv, U, w_cnt, stage, lane);
         pend = cw;
         pend_dst = rec + pos + gw;
         pos += gw + cw;
@@ -862,10 +885,10 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         }
         if (pend) {
             wave_lds_sync();
-            copy_out<ITEMS>(pend, pend_dst, kvbuf, lane);
+            copy_out<ITEMS>(pend, pend_dst, stage, lane);
         }
         wave_lds_sync();  // the staged words are read before they are replaced
-        pack_stage<ITEMS>(vals, count, w, kvbuf, lane);
+        pack_stage<ITEMS>(vals, count, w, stage, lane);
         pend = words_for(count, w);
         pend_dst = rec + pos;
         pos += pend;
@@ -895,7 +918,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     }
     if (!over && pend) {
         wave_lds_sync();
-        copy_out<ITEMS>(pend, pend_dst, kvbuf, lane);
+        copy_out<ITEMS>(pend, pend_dst, stage, lane);
         wave_lds_sync();
     }
 
@@ -931,19 +954,6 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
     }
 }
 
-template <int ITEMS>
-struct EncodeSmem {
-    static constexpr uint32_t B = 64 * ITEMS;
-    static constexpr uint32_t kKvWords = 64 * (ITEMS + 4);
-    // run tables: uniq[0, B), start[0, B] at B, and per-lane scratch words
-    // for the branch-free run stores at 2B + 64 and 2B + 128
-    static constexpr uint32_t kWorkA = kCounterWords > 2 * B + 192 ? kCounterWords : 2 * B + 192;
-    static constexpr uint32_t kWorkWords = kWorkA > kKvWords ? kWorkA : kKvWords;
-    // kvbuf doubles as the packer's staging buffer, read in steps of 256 words
-    static_assert((48 * ITEMS + 255) / 256 * 256 <= kKvWords, "staging reads stay in kvbuf");
-    __align__(16) uint32_t kvbuf[kKvWords];
-    __align__(16) uint32_t work[kWorkWords];
-};
 
 // Three-step compaction: one workgroup per block, block index = workgroup
 // index.  Full blocks take the path without bounds checks, the partial last
@@ -954,8 +964,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
     __shared__ EncodeSmem<ITEMS> sm;
     const uint32_t b = blockIdx.x;
     const uint64_t left = a.n - (uint64_t)b * B;
-    if (left >= B) encode_block<ITEMS, true, false>(a, b, B, sm.kvbuf, sm.work);
-    else encode_block<ITEMS, false, false>(a, b, (uint32_t)left, sm.kvbuf, sm.work);
+    if (left >= B) encode_block<ITEMS, true, false>(a, b, B, sm.buf);
+    else encode_block<ITEMS, false, false>(a, b, (uint32_t)left, sm.buf);
 }
 
 // The same with no early fields beside the key fields (EARLY = 0) and the
@@ -969,8 +979,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void en
     __shared__ EncodeSmem<ITEMS> sm;
     const uint32_t b = blockIdx.x;
     const uint64_t left = a.n - (uint64_t)b * B;
-    if (left >= B) encode_block<ITEMS, true, false, 0>(a, b, B, sm.kvbuf, sm.work);
-    else encode_block<ITEMS, false, false, 0>(a, b, (uint32_t)left, sm.kvbuf, sm.work);
+    if (left >= B) encode_block<ITEMS, true, false, 0>(a, b, B, sm.buf);
+    else encode_block<ITEMS, false, false, 0>(a, b, (uint32_t)left, sm.buf);
 }
 
 // Single-pass compaction: blocks are numbered by a ticket taken when the
@@ -983,8 +993,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
     if (threadIdx.x == 0) t = atomicAdd(a.ticket, 1u);
     const uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
     const uint64_t left = a.n - (uint64_t)b * B;
-    if (left >= B) encode_block<ITEMS, true, true>(a, b, B, sm.kvbuf, sm.work);
-    else encode_block<ITEMS, false, true>(a, b, (uint32_t)left, sm.kvbuf, sm.work);
+    if (left >= B) encode_block<ITEMS, true, true>(a, b, B, sm.buf);
+    else encode_block<ITEMS, false, true>(a, b, (uint32_t)left, sm.buf);
 }
 
 // Single pass, a snapshot with no particles: header only.
@@ -1026,7 +1036,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
         const uint32_t end = min(item + tile, total);
         for (uint32_t g = item; g < end; g++) {
             const uint32_t j = find_job(prefix, njobs, g);
-            encode_block<ITEMS, true, false>(jobs[j], g - prefix[j], B, sm.kvbuf, sm.work);
+            encode_block<ITEMS, true, false>(jobs[j], g - prefix[j], B, sm.buf);
             __syncthreads();
         }
     }
@@ -1045,7 +1055,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ITEMS == 16 
     if (g >= L->total_full) return;
     const uint32_t* prefix = L->full_prefix;
     const uint32_t j = find_job(prefix, L->njobs, g);
-    encode_block<ITEMS, true, false, ITEMS == 16 ? 0 : 3>(jobs[j], g - prefix[j], B, sm.kvbuf, sm.work);
+    encode_block<ITEMS, true, false, ITEMS == 16 ? 0 : 3>(jobs[j], g - prefix[j], B, sm.buf);
 }
 
 // The partial last block of each snapshot that has one.
@@ -1059,7 +1069,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ITEMS == 16 
         const EncodeArgs& a = jobs[__builtin_amdgcn_readfirstlane((int)L->tail_jobs[t])];
         const uint32_t b = a.nblocks - 1;
         const uint32_t nb = (uint32_t)(a.n - (uint64_t)b * B);
-        encode_block<ITEMS, false, false, ITEMS == 16 ? 0 : 3>(a, b, nb, sm.kvbuf, sm.work);
+        encode_block<ITEMS, false, false, ITEMS == 16 ? 0 : 3>(a, b, nb, sm.buf);
         __syncthreads();
     }
 }
