@@ -808,29 +808,125 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         pend_dst = rec + pos + gw;
         pos += gw + cw;
     }
-    for (uint32_t f = 0; f < F && !over; f++) {
-        if constexpr (EARLY == 0) {
+    // One field's section once its codes are staged in LDS (input order, at
+    // `work` in the padded blocked layout): lo and field word, the codes
+    // permuted to sorted order (a key field's in-segment offsets: its low
+    // `width` bits), packed; its outliers.  Returns false when the block is
+    // stored raw (or, for a wide field, left to the generic encoder).
+    auto section = [&](uint32_t f, const FieldCodes& c, bool key, uint32_t width, uint32_t vmax,
+                       uint32_t no) -> bool {
+        if (wide) {
+            over = true;
+            return false;
+        }
+        const uint32_t w = bit_width(key ? wave_max_u32(vmax) : c.qmax);
+        const uint32_t nout = c.clean ? 0u : wave_sum_u32(no);
+        if (pos + 2 + words_for(nb, w) + 2 * nout > cap) {
+            over = true;
+            return false;
+        }
+        if (lane == 0) {
+            rec[pos] = f2u(c.lo);
+            rec[pos + 1] = w | (nout << 5);
+        }
+        pos += 2;
+        // permute to sorted order through LDS
+        wave_lds_sync();
+        uint32_t vals[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++)
+            vals[j] = (FULL || lane * ITEMS + j < nb)
+                          ? __builtin_amdgcn_ubfe(work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)], 1u, width)
+                          : 0u;
+        if (pend) {
+            wave_lds_sync();
+            copy_out<ITEMS>(pend, pend_dst, stage, lane);
+        }
+        wave_lds_sync();  // the staged words are read before they are replaced
+        pack_stage<ITEMS>(vals, nb, w, stage, lane);
+        pend = words_for(nb, w);
+        pend_dst = rec + pos;
+        pos += pend;
+        if (nout) {
+            // outlier flags of the sorted positions, read again from the staging
+            uint32_t flags = 0;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++)
+                if ((FULL || lane * ITEMS + j < nb) &&
+                    (work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)] & 1u))
+                    flags |= 1u << j;
+            const uint32_t cnt = __builtin_popcount(flags);
+            uint32_t k = wave_incl_scan_u32(cnt) - cnt;
+            uint32_t* ol = rec + pos;
+            const float* xf = a.x[f] + base;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                if ((flags >> j) & 1u) {
+                    ol[2 * k] = lane * ITEMS + j;
+                    ol[2 * k + 1] = f2u(xf[kv[j] & 0xFFFFu]);
+                    k++;
+                }
+            }
+            pos += 2 * nout;
+        }
+        wave_lds_sync();  // staging reads done before the next field overwrites it
+        return true;
+    };
+    uint4* const mine = reinterpret_cast<uint4*>(work + lane * (ITEMS + 4));
+    if constexpr (EARLY == 0) {
+        // The key fields' codes are in registers; each other field is
+        // fetched while its predecessor is staged and packed.
+        for (uint32_t f = 0; f < KF && !over; f++) {
             // the permutation's LDS offsets are recomputed per field instead
             // of being held in registers across the loop
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) asm volatile("" : "+v"(kv[j]));
+            FieldCodes c{0.0f, 0u, true, false};
+            uint32_t width = 0, vmax = 0, no = 0;
+            // one wave-uniform branch per source, each reading its own
+            // registers (the empty asm keeps the compiler from merging the
+            // branches into a select per value)
+            switch (f) {
+#define GPZ_STAGE(N)                                                        \
+    case N:                                                                 \
+        c = ck[N];                                                          \
+        width = sk[N];                                                      \
+        stage_codes<ITEMS, true>(qk[N], width, c.clean, mine, vmax, no);    \
+        asm volatile("");                                                   \
+        break;
+                GPZ_STAGE(0) GPZ_STAGE(1) GPZ_STAGE(2)
+#undef GPZ_STAGE
+            }
+            if (!section(f, c, true, width, vmax, no)) break;
         }
-        uint32_t vals[ITEMS];
-        uint32_t w, count, nout = 0;
-        {
-            FieldCodes c{0.0f, 0u, true};
+        float xn[ITEMS];
+        if (KF < F && !over) load_block<ITEMS, FULL>(a.x[KF], base, nb, lane, xn);
+        for (uint32_t f = KF; f < F && !over; f++) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) asm volatile("" : "+v"(kv[j]));
+            uint32_t q[ITEMS];
+            const FieldCodes c =
+                quantize_field<ITEMS, FULL>(xn, nb, lane, a.inv[f], a.twoeb[f], a.eb[f], q);
+            if (f + 1 < F) load_block<ITEMS, FULL>(a.x[f + 1], base, nb, lane, xn);
+            wide = wide || c.wide;
+            uint32_t vmax = 0, no = 0;
+            stage_codes<ITEMS, false>(q, 24u, c.clean, mine, vmax, no);
+            if (!section(f, c, false, 24u, vmax, no)) break;
+        }
+    } else {
+        for (uint32_t f = 0; f < F && !over; f++) {
+            FieldCodes c{0.0f, 0u, true, false};
             uint32_t width = 24, vmax = 0, no = 0;
             bool key = false;
-            // The field's codes go to LDS in input order (for the permutation
-            // below).  Key fields and the early fields are already in
-            // registers: one wave-uniform branch per source, each reading its
-            // own registers (the empty asm keeps the compiler from merging the
-            // branches into a select per value).  Later fields are loaded and
-            // quantized here.  The packed value is the code's in-segment
-            // offset for a key field (its low sk bits), the whole code
-            // otherwise.
-            uint4* mine = reinterpret_cast<uint4*>(work + lane * (ITEMS + 4));
-            const uint32_t src = f < KF ? f : (f - KF < (uint32_t)EARLY ? 3 + (f - KF) : 6u);
+            // The field's codes go to LDS in input order (for the
+            // permutation).  Key fields and the early fields are already in
+            // registers: one wave-uniform branch per source, each reading
+            // its own registers (the empty asm keeps the compiler from
+            // merging the branches into a select per value).  Later fields
+            // are loaded and quantized here.  The packed value is the code's
+            // in-segment offset for a key field (its low sk bits), the whole
+            // code otherwise.
+            const uint32_t src = f < KF ? f : 3 + (f - KF);
             switch (src) {
 #define GPZ_STAGE(N, QA, C, KEY, WIDTH)                                  \
     case N:                                                              \
@@ -857,64 +953,8 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
                     break;
                 }
             }
-            if (wide) {
-                over = true;
-                break;
-            }
-            const float lo = c.lo;
-            w = bit_width(key ? wave_max_u32(vmax) : c.qmax);
-            nout = c.clean ? 0u : wave_sum_u32(no);
-            count = nb;
-            if (pos + 2 + words_for(nb, w) + 2 * nout > cap) {
-                over = true;
-                break;
-            }
-            if (lane == 0) {
-                rec[pos] = f2u(lo);
-                rec[pos + 1] = w | (nout << 5);
-            }
-            pos += 2;
-            // permute to sorted order through LDS
-            wave_lds_sync();
-#pragma unroll
-            for (int j = 0; j < ITEMS; j++)
-                vals[j] = (FULL || lane * ITEMS + j < nb)
-                              ? __builtin_amdgcn_ubfe(work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)], 1u,
-                                                      width)
-                              : 0u;
+            if (!section(f, c, key, width, vmax, no)) break;
         }
-        if (pend) {
-            wave_lds_sync();
-            copy_out<ITEMS>(pend, pend_dst, stage, lane);
-        }
-        wave_lds_sync();  // the staged words are read before they are replaced
-        pack_stage<ITEMS>(vals, count, w, stage, lane);
-        pend = words_for(count, w);
-        pend_dst = rec + pos;
-        pos += pend;
-        if (nout) {
-            // outlier flags of the sorted positions, read again from the staging
-            uint32_t flags = 0;
-#pragma unroll
-            for (int j = 0; j < ITEMS; j++)
-                if ((FULL || lane * ITEMS + j < nb) &&
-                    (work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)] & 1u))
-                    flags |= 1u << j;
-            const uint32_t c = __builtin_popcount(flags);
-            uint32_t k = wave_incl_scan_u32(c) - c;
-            uint32_t* ol = rec + pos;
-            const float* xf = a.x[f] + base;
-#pragma unroll
-            for (int j = 0; j < ITEMS; j++) {
-                if ((flags >> j) & 1u) {
-                    ol[2 * k] = lane * ITEMS + j;
-                    ol[2 * k + 1] = f2u(xf[kv[j] & 0xFFFFu]);
-                    k++;
-                }
-            }
-            pos += 2 * nout;
-        }
-        wave_lds_sync();  // staging reads done before the next field overwrites it
     }
     if (!over && pend) {
         wave_lds_sync();
