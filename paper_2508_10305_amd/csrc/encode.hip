@@ -43,6 +43,21 @@ __device__ __forceinline__ uint32_t pad_addr(uint32_t p) {
     return p + 4 * (p / ITEMS);
 }
 
+// Sort items carry (segment ID << 16) | byte offset of the particle's word
+// in the padded blocked layout, so that the per-field permutation reads take
+// their LDS address straight from the item.
+__device__ __forceinline__ uint32_t staged_at(const uint32_t* work, uint32_t item) {
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(work) +
+                                              (item & 0xFFFFu));
+}
+
+// The particle index of an item: padded word p + 4*(p/ITEMS) back to p.
+template <int ITEMS>
+__device__ __forceinline__ uint32_t index_of(uint32_t item) {
+    const uint32_t w = (item & 0xFFFFu) >> 2;
+    return w - 4u * (w / (ITEMS + 4));
+}
+
 // Quantizer: t = (x - lo) * inv (two IEEE float ops), q = rint(t) when t lies
 // in [0, 2^24-1] (else 0); the value stays on the grid only when the float32
 // error of xr = fma(q, 2eb, lo) is below eb (which bounds the exact error
@@ -729,7 +744,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         for (int ax = 0; ax < 3; ax++)
             if ((uint32_t)ax < KF) key = (key << K) | (qk[ax][j] >> (sk[ax] + 1));
         uint32_t i = lane * ITEMS + j;
-        kv[j] = (key << 16) | i;
+        kv[j] = (key << 16) | (4u * pad_addr<ITEMS>(i));
         if (FULL || i < nb) keyor |= key;
     }
     keyor = wave_or_u32(keyor);
@@ -836,7 +851,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 #pragma unroll
         for (int j = 0; j < ITEMS; j++)
             vals[j] = (FULL || lane * ITEMS + j < nb)
-                          ? __builtin_amdgcn_ubfe(work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)], 1u, width)
+                          ? __builtin_amdgcn_ubfe(staged_at(work, kv[j]), 1u, width)
                           : 0u;
         if (pend) {
             wave_lds_sync();
@@ -853,7 +868,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 #pragma unroll
             for (int j = 0; j < ITEMS; j++)
                 if ((FULL || lane * ITEMS + j < nb) &&
-                    (work[pad_addr<ITEMS>(kv[j] & 0xFFFFu)] & 1u))
+                    (staged_at(work, kv[j]) & 1u))
                     flags |= 1u << j;
             const uint32_t cnt = __builtin_popcount(flags);
             uint32_t k = wave_incl_scan_u32(cnt) - cnt;
@@ -863,7 +878,7 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
             for (int j = 0; j < ITEMS; j++) {
                 if ((flags >> j) & 1u) {
                     ol[2 * k] = lane * ITEMS + j;
-                    ol[2 * k + 1] = f2u(xf[kv[j] & 0xFFFFu]);
+                    ol[2 * k + 1] = f2u(xf[index_of<ITEMS>(kv[j])]);
                     k++;
                 }
             }
@@ -989,7 +1004,8 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             uint32_t p = lane * ITEMS + j;
-            if (FULL || p < nb) a.perm[base + p] = (uint32_t)(base + (raw ? p : (kv[j] & 0xFFFFu)));
+            if (FULL || p < nb)
+                a.perm[base + p] = (uint32_t)(base + (raw ? p : index_of<ITEMS>(kv[j])));
         }
     }
 }
