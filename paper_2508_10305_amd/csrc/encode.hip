@@ -107,8 +107,9 @@ struct FieldCodes {
     bool wide;
 };
 
-// Quantize one field of the block (Sec. 4.1).  Codes are returned as
-// 2*q + outlier per value (0 beyond the block).
+// Quantize one field of the block (Sec. 4.1).  Codes are returned as q per
+// value for a field without outliers (`clean`), as 2*q + outlier otherwise
+// (0 beyond the block).
 //
 // Fast path, exact for a field without outliers.  Every finite value lies at
 // or above the block minimum lo, so t = (x - lo) * inv is never below -0, and
@@ -159,7 +160,7 @@ __device__ __forceinline__ FieldCodes quantize_field(const float (&v)[ITEMS], ui
         const float xr = __builtin_fmaf(r, twoeb, lo);
         emax = __builtin_elementwise_maximum(emax, valid ? __builtin_fabsf(xr - v[j]) : 0.0f);
         rmax = fmaxf(rmax, valid ? r : 0.0f);
-        q[j] = valid ? (uint32_t)(r + r) : 0u;
+        q[j] = valid ? (uint32_t)r : 0u;
     }
     uint32_t qmax = wave_max_u32(rmax <= kQMax ? (uint32_t)rmax : 0xFFFFFFFFu);
     if (__all(emax < eb) && qmax <= 0xFFFFFFu) return {lo, qmax, true, false};
@@ -448,16 +449,16 @@ __device__ __forceinline__ void radix_pass(uint32_t (&kv)[ITEMS], uint32_t sh, u
     wave_lds_sync();
 }
 
-// A field's codes (2*q + outlier per value) into lane l's LDS row.  A key
-// field also needs the largest of its in-segment offsets (code bits below
-// its segment shift, width bits wide); a field with outliers needs their
-// number.
+// A field's codes (q, or 2*q + outlier for a field with outliers) into lane
+// l's LDS row.  A key field also needs the largest of its in-segment offsets
+// (the low `width` bits of q); a field with outliers needs their number.
 template <int ITEMS, bool KEY>
 __device__ __forceinline__ void stage_codes(const uint32_t (&q)[ITEMS], uint32_t width, bool clean,
                                             uint4* mine, uint32_t& vmax, uint32_t& no) {
     if (KEY) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) vmax = max(vmax, __builtin_amdgcn_ubfe(q[j], 1u, width));
+        for (int j = 0; j < ITEMS; j++)
+            vmax = max(vmax, __builtin_amdgcn_ubfe(q[j], clean ? 0u : 1u, width));
     }
     if (!clean) {
 #pragma unroll
@@ -742,7 +743,8 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         uint32_t key = 0;
 #pragma unroll
         for (int ax = 0; ax < 3; ax++)
-            if ((uint32_t)ax < KF) key = (key << K) | (qk[ax][j] >> (sk[ax] + 1));
+            if ((uint32_t)ax < KF)
+                key = (key << K) | (qk[ax][j] >> (sk[ax] + (ck[ax].clean ? 0u : 1u)));
         uint32_t i = lane * ITEMS + j;
         kv[j] = (key << 16) | (4u * pad_addr<ITEMS>(i));
         if (FULL || i < nb) keyor |= key;
@@ -847,12 +849,21 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         pos += 2;
         // permute to sorted order through LDS
         wave_lds_sync();
+        // the packed value: q of a clean non-key field as it is, else the
+        // code's grid index (without the outlier bit) cut to `width` bits
         uint32_t vals[ITEMS];
+        if (!key && c.clean) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++)
-            vals[j] = (FULL || lane * ITEMS + j < nb)
-                          ? __builtin_amdgcn_ubfe(staged_at(work, kv[j]), 1u, width)
-                          : 0u;
+            for (int j = 0; j < ITEMS; j++)
+                vals[j] = (FULL || lane * ITEMS + j < nb) ? staged_at(work, kv[j]) : 0u;
+        } else {
+            const uint32_t s0 = c.clean ? 0u : 1u;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++)
+                vals[j] = (FULL || lane * ITEMS + j < nb)
+                              ? __builtin_amdgcn_ubfe(staged_at(work, kv[j]), s0, width)
+                              : 0u;
+        }
         if (pend) {
             wave_lds_sync();
             copy_out<ITEMS>(pend, pend_dst, stage, lane);
