@@ -512,8 +512,14 @@ def main():
         best, _ = hbm_reference(S, reps=5)
         extra["hbm_reference"] = {"read_GBps": best["read"]["GBps"],
                                   "copy_GBps": best["copy"]["GBps"],
+                                  "read4_write1_GBps": best["mix_4r1w"]["GBps"],
+                                  "read1_write4_GBps": best["mix_1r4w"]["GBps"],
                                   "read_shape": {k: best["read"][k] for k in ("wg_per_cu", "unroll", "nt")},
                                   "copy_shape": {k: best["copy"][k] for k in ("wg_per_cu", "unroll", "nt")}}
+        # the dominant kernels against the probe of their own traffic mix
+        extra["vs_mix_probe"] = {
+            "encoder": round(kernels["encode"]["algorithmic_GBps"] / best["mix_4r1w"]["GBps"], 4),
+            "decoder": round(kernels["decode"]["algorithmic_GBps"] / best["mix_1r4w"]["GBps"], 4)}
         extra["f64_cosmology"] = f64_figures(gpz, torch, host, args.rel, max(3, args.steps // 4))
         del fields, outs, comp, stream, perm
         torch.cuda.empty_cache()
@@ -643,6 +649,8 @@ def membench_lib():
     L.gpzb_read.restype = ctypes.c_int
     L.gpzb_copy.argtypes = [vp, vp, u64, u32, u32, u32, vp]
     L.gpzb_copy.restype = ctypes.c_int
+    L.gpzb_mix.argtypes = [vp, vp, u64, u32, u32, u32, u32, u32, vp]
+    L.gpzb_mix.restype = ctypes.c_int
     return L
 
 
@@ -661,15 +669,23 @@ def hbm_reference(nbytes: int, reps: int = 10, full: bool = False):
     per_cu = (1, 2, 4, 8, 16, 32) if full else (2, 4, 8, 16)
     unrolls = (1, 2, 4, 8, 16) if full else (2, 4, 8)
     table = []
-    for kind in ("read", "copy"):
+    # the encoder's mix (read 4 : write 1) over the whole buffer, the
+    # decoder's (read 1 : write 4) writing the whole buffer
+    enc_read = nbytes // 65536 * 65536
+    dec_read = nbytes // 4 // 65536 * 65536
+    for kind in ("read", "copy", "mix_4r1w", "mix_1r4w"):
         for k in per_cu:
-            for u in unrolls:
+            for u in (unrolls if kind in ("read", "copy") else (1, 2, 4)):
                 for nt in (0, 1):
                     def call():
                         if kind == "read":
                             rc = L.gpzb_read(x.data_ptr(), nbytes, cus * k, u, nt, sink.data_ptr(), s)
-                        else:
+                        elif kind == "copy":
                             rc = L.gpzb_copy(x.data_ptr(), y.data_ptr(), nbytes, cus * k, u, nt, s)
+                        elif kind == "mix_4r1w":
+                            rc = L.gpzb_mix(x.data_ptr(), y.data_ptr(), enc_read, 4, 1, cus * k, u, nt, s)
+                        else:
+                            rc = L.gpzb_mix(x.data_ptr(), y.data_ptr(), dec_read, 1, 4, cus * k, u, nt, s)
                         assert rc == 0, rc
                     call()
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -679,11 +695,12 @@ def hbm_reference(nbytes: int, reps: int = 10, full: bool = False):
                     e1.record()
                     torch.cuda.synchronize()
                     ms = e0.elapsed_time(e1) / reps
-                    moved = nbytes * (1 if kind == "read" else 2)
+                    moved = {"read": nbytes, "copy": 2 * nbytes, "mix_4r1w": enc_read * 5 // 4,
+                             "mix_1r4w": dec_read * 5}[kind]
                     table.append({"kind": kind, "wg_per_cu": k, "unroll": u, "nt": nt,
                                   "ms": round(ms, 4), "GBps": round(moved / (ms * 1e-3) / 1e9, 1)})
     best = {kind: max((r for r in table if r["kind"] == kind), key=lambda r: r["GBps"])
-            for kind in ("read", "copy")}
+            for kind in ("read", "copy", "mix_4r1w", "mix_1r4w")}
     del x, y
     torch.cuda.empty_cache()
     return best, table
@@ -710,6 +727,7 @@ def bench_copy(args):
     ms = e0.elapsed_time(e1) / args.steps
     print(json.dumps({"metric": "achievable HBM GB/s (read; copy = read + write)", "form": "copy",
                       "bytes": S, "best_read": best["read"], "best_copy": best["copy"],
+                      "best_read4_write1": best["mix_4r1w"], "best_read1_write4": best["mix_1r4w"],
                       "torch_copy_GBps": round(2 * S / (ms * 1e-3) / 1e9, 2),
                       "sweep": table}), flush=True)
 

@@ -29,6 +29,13 @@ int gpzb_read(const void *d_x, uint64_t bytes, uint32_t grid, uint32_t unroll, u
 int gpzb_copy(const void *d_x, void *d_y, uint64_t bytes, uint32_t grid, uint32_t unroll,
               uint32_t nt, void *stream);
 
+/* Reads read_bytes from d_x and writes read_bytes * ratio_write /
+ * ratio_read to d_y, in the ratio 4:1 (about the encoder's input-to-record
+ * traffic) or 1:4 (the decoder's).  read_bytes must be a multiple of 64 KB;
+ * d_y must hold the bytes written.  unroll 1, 2 or 4. */
+int gpzb_mix(const void *d_x, void *d_y, uint64_t read_bytes, uint32_t ratio_read,
+             uint32_t ratio_write, uint32_t grid, uint32_t unroll, uint32_t nt, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

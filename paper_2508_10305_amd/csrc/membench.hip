@@ -72,6 +72,57 @@ __global__ __launch_bounds__(256) void copy_chunks(const u32x4* __restrict__ x,
     }
 }
 
+// Traffic in the ratio of the compressor's kernels: every wave reads RD and
+// writes WR 16-byte vectors per unit of U * 256 vectors (RD = 4, WR = 1:
+// about the encoder's input-to-record mix; RD = 1, WR = 4: the decoder's).
+// Unit c reads x[RD*c*U*256 ...) and writes y[WR*c*U*256 ...); all of a
+// lane's loads are issued before its stores.  nunits = whole units only.
+template <int U, int RD, int WR, bool NT>
+__global__ __launch_bounds__(256) void mix_chunks(const u32x4* __restrict__ x,
+                                                  u32x4* __restrict__ y, uint64_t nunits) {
+    constexpr uint64_t kUnit = (uint64_t)U * 256;
+    for (uint64_t c = blockIdx.x; c < nunits; c += gridDim.x) {
+        const u32x4* xs = x + c * RD * kUnit;
+        u32x4* ys = y + c * WR * kUnit;
+        u32x4 v[U * RD];
+#pragma unroll
+        for (int k = 0; k < U * RD; k++) v[k] = load16<NT>(xs + 256 * k + threadIdx.x);
+#pragma unroll
+        for (int k = 0; k < U * WR; k++) {
+            u32x4 t = v[k % (U * RD)];
+            if constexpr (RD > WR) {
+#pragma unroll
+                for (int r = 1; r < RD / WR; r++) t ^= v[(k + r * U * WR) % (U * RD)];
+            }
+            t.x ^= (uint32_t)k;
+            store16<NT>(ys + 256 * k + threadIdx.x, t);
+        }
+    }
+}
+
+template <int U, int RD, int WR>
+hipError_t launch_mix_u(const void* x, void* y, uint64_t nunits, uint32_t grid, uint32_t nt,
+                        hipStream_t s) {
+    if (nt) hipLaunchKernelGGL((mix_chunks<U, RD, WR, true>), dim3(grid), dim3(256), 0, s,
+                               static_cast<const u32x4*>(x), static_cast<u32x4*>(y), nunits);
+    else hipLaunchKernelGGL((mix_chunks<U, RD, WR, false>), dim3(grid), dim3(256), 0, s,
+                            static_cast<const u32x4*>(x), static_cast<u32x4*>(y), nunits);
+    return hipGetLastError();
+}
+
+template <int RD, int WR>
+hipError_t launch_mix(const void* x, void* y, uint64_t nunits_of_1, uint32_t grid,
+                      uint32_t unroll, uint32_t nt, hipStream_t s) {
+    // nunits_of_1: units of one vector per lane (256 vectors); a unit of U
+    // per lane covers U of them
+    switch (unroll) {
+        case 1: return launch_mix_u<1, RD, WR>(x, y, nunits_of_1, grid, nt, s);
+        case 2: return launch_mix_u<2, RD, WR>(x, y, nunits_of_1 / 2, grid, nt, s);
+        case 4: return launch_mix_u<4, RD, WR>(x, y, nunits_of_1 / 4, grid, nt, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int U>
 hipError_t launch_read_u(const void* x, uint64_t nv, uint32_t grid, uint32_t nt, uint32_t* sink,
                          hipStream_t s) {
@@ -131,6 +182,21 @@ int gpzb_copy(const void* d_x, void* d_y, uint64_t bytes, uint32_t grid, uint32_
         case 16: e = launch_copy_u<16>(d_x, d_y, nv, grid, nt, s); break;
         default: return -1;
     }
+    return e == hipSuccess ? 0 : -4;
+}
+
+int gpzb_mix(const void* d_x, void* d_y, uint64_t read_bytes, uint32_t ratio_read,
+             uint32_t ratio_write, uint32_t grid, uint32_t unroll, uint32_t nt, void* stream) {
+    const bool shape = (ratio_read == 4 && ratio_write == 1) || (ratio_read == 1 && ratio_write == 4);
+    if (!shape || !d_x || !d_y || grid < 1 || read_bytes % (4096u * 4u * 4u) != 0 ||
+        (reinterpret_cast<uintptr_t>(d_x) & 15u) || (reinterpret_cast<uintptr_t>(d_y) & 15u))
+        return -1;
+    if (unroll != 1 && unroll != 2 && unroll != 4) return -1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // units of one 16-byte vector per lane on the read side
+    const uint64_t nunits = read_bytes / 16 / 256 / ratio_read;
+    const hipError_t e = ratio_read == 4 ? launch_mix<4, 1>(d_x, d_y, nunits, grid, unroll, nt, s)
+                                         : launch_mix<1, 4>(d_x, d_y, nunits, grid, unroll, nt, s);
     return e == hipSuccess ? 0 : -4;
 }
 

@@ -195,3 +195,28 @@ def test_injected_allocation_failure(gpz, monkeypatch):
     assert L.gpz_error_stats(ctypes.cast(fake, ctypes.c_void_p), ctypes.cast(fake, ctypes.c_void_p),
                              None, 5000, 3, ebs.ctypes.data_as(ctypes.c_void_p), res, None, None,
                              0, None) == gpz.GPZ_ENOMEM
+
+
+def test_bandwidth_probes_export_and_check_arguments(gpz):
+    """libgpzbench.so (the achievable-bandwidth probes beside the roofline
+    peak) exports the probes of include/gpz_bench.h and refuses bad shapes
+    before launching anything."""
+    from paper_2508_10305_amd import build
+    if not os.path.exists(build.BENCH_LIB):
+        build.build_lib()
+    L = ctypes.CDLL(build.BENCH_LIB)
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "gpz_bench.h")).read(),
+                  flags=re.S)
+    names = sorted(set(re.findall(r"\b(gpzb_[a-z_0-9]+)\s*\(", text)))
+    assert names == ["gpzb_copy", "gpzb_mix", "gpzb_read"]
+    for n in names:
+        assert hasattr(L, n), n
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    L.gpzb_mix.argtypes = [vp, vp, u64, u32, u32, u32, u32, u32, vp]
+    L.gpzb_mix.restype = ctypes.c_int
+    fake = 0x10000  # never dereferenced on the host
+    assert L.gpzb_mix(None, fake, 65536, 4, 1, 1, 1, 0, None) == -1      # null source
+    assert L.gpzb_mix(fake, fake, 65536, 2, 1, 1, 1, 0, None) == -1      # ratio not 4:1 / 1:4
+    assert L.gpzb_mix(fake, fake, 65536 + 16, 4, 1, 1, 1, 0, None) == -1  # not whole units
+    assert L.gpzb_mix(fake, fake, 65536, 1, 4, 1, 8, 0, None) == -1      # unroll 8
+    assert L.gpzb_mix(fake, fake, 65536, 1, 4, 0, 1, 0, None) == -1      # empty grid
