@@ -437,7 +437,7 @@ __global__ __launch_bounds__(64) void decode_batch(const DecodeArgs* __restrict_
 // Direct form of decode_batch: one workgroup per block of the batch's
 // capacity (no loop around the block, so a smaller register budget).
 template <int ITEMS>
-__global__ __launch_bounds__(64) void decode_batch_direct(const DecodeArgs* __restrict__ jobs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ITEMS == 32 ? 3 : 8))) void decode_batch_direct(const DecodeArgs* __restrict__ jobs,
                                                           const BatchLaunch* __restrict__ L) {
     __shared__ __align__(16) DecodeShared<ITEMS> sm;
     const uint32_t g = blockIdx.x;
