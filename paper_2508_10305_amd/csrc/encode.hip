@@ -45,10 +45,10 @@ __device__ __forceinline__ uint32_t pad_addr(uint32_t p) {
 
 // Sort items carry (segment ID << 16) | byte offset of the particle's word
 // in the padded blocked layout, so that the per-field permutation reads take
-// their LDS address straight from the item.
-__device__ __forceinline__ uint32_t staged_at(const uint32_t* work, uint32_t item) {
-    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(work) +
-                                              (item & 0xFFFFu));
+// their LDS address straight from the item.  Once the runs are coded the
+// segment IDs are cleared from the items, which leaves the offset alone.
+__device__ __forceinline__ uint32_t staged_at(const uint32_t* work, uint32_t offset) {
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(work) + offset);
 }
 
 // The particle index of an item: padded word p + 4*(p/ITEMS) back to p.
@@ -788,6 +788,9 @@ __device__ __forceinline__ void encode_block(const EncodeArgs& a, uint32_t b, ui
         if (lane == 0) start[U] = nb;
     }
     wave_lds_sync();
+    // from here on the items are only LDS offsets (the permutation)
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) kv[j] &= 0xFFFFu;
     // delta coding of the distinct IDs (stored as delta - 1) and counts - 1,
     // kept in registers until they are packed
     uint32_t gv[ITEMS], cv[ITEMS];
