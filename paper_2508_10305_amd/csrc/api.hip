@@ -206,8 +206,11 @@ int compress_impl(const void* const* h_fields, bool f64, uint64_t n, uint32_t F,
 
     Timer tm(s);
     tm.begin(kPrepare);
+    // the single pass also needs its look-back words zeroed; the three steps
+    // only the counters and superblock sums that follow them
     int rc = to_status(
-        launch_fill_u32(reinterpret_cast<uint32_t*>(w.state), 0u, w.clear_words, s));
+        single ? launch_fill_u32(reinterpret_cast<uint32_t*>(w.state), 0u, w.clear_words, s)
+               : launch_fill_u32(w.ticket, 0u, w.clear_words - 2 * nb, s));
     tm.end();
     tm.begin(kEncode);
     if (rc == GPZ_OK) rc = to_status(generic ? launch_encode_generic(ea, false, s)
