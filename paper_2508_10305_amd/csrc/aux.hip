@@ -89,6 +89,17 @@ __global__ __launch_bounds__(256) void copy_records(CopyArgs a) {
     copy_body(a, b, threadIdx.x & 63u);
 }
 
+// Direct form: one wave per block of the batch's capacity (4 per
+// workgroup), as the plain copy; waves past the bound jobs' blocks exit.
+__global__ __launch_bounds__(256) void copy_records_batch_direct(const CopyArgs* jobs,
+                                                                 const BatchLaunch* L) {
+    const uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= L->total_blocks) return;
+    const uint32_t* prefix = L->block_prefix;
+    const uint32_t j = find_job(prefix, L->njobs, g);
+    copy_body(jobs[j], g - prefix[j], threadIdx.x & 63u);
+}
+
 __global__ __launch_bounds__(256) void copy_records_batch(const CopyArgs* jobs,
                                                           const BatchLaunch* L) {
     const uint32_t total = L->total_blocks, njobs = L->njobs;
@@ -473,7 +484,11 @@ hipError_t launch_scan_batch(const ScanArgs* jobs, const BatchLaunch* L, const B
 
 hipError_t launch_copy_batch(const CopyArgs* jobs, const BatchLaunch* L, const BatchShape& S,
                              hipStream_t s) {
-    hipLaunchKernelGGL(copy_records_batch, dim3(S.copy_grid), dim3(256), 0, s, jobs, L);
+    if (S.grid)
+        hipLaunchKernelGGL(copy_records_batch, dim3(S.copy_grid), dim3(256), 0, s, jobs, L);
+    else
+        hipLaunchKernelGGL(copy_records_batch_direct, dim3((S.direct_grid + 3) / 4), dim3(256), 0,
+                           s, jobs, L);
     return hipGetLastError();
 }
 

@@ -361,7 +361,7 @@ int gpz_batch_create(gpz_batch** out, const gpz_job* jobs, uint32_t njobs, const
     b->shape.grid = c.grid;
     b->shape.direct_grid = (uint32_t)(b->max_blocks ? b->max_blocks : 1);
     b->shape.scan_grid = b->max_jobs < 256 ? b->max_jobs : 256;
-    b->shape.copy_grid = c.grid ? c.grid : 2048;  // 4-wave workgroups copying
+    b->shape.copy_grid = c.grid ? c.grid : 2048;  // persistent grids: 4-wave workgroups copying
     b->shape.tail_grid = b->max_jobs < 1024 ? b->max_jobs : 1024;  // every tail at once
     const uint32_t mj = b->max_jobs;
     const uint64_t mb = b->max_blocks, ms = b->max_super;

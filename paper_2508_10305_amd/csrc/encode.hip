@@ -1112,20 +1112,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void en
     }
 }
 
-// Direct form of encode_batch: one workgroup per full block of the batch's
+// Direct form of encode_batch: one workgroup per block of the batch's
 // capacity; workgroups past the bound jobs' blocks exit at once.  No loop
 // around the block, so the compiler keeps the register budget of the plain
-// kernel.
+// kernel.  Up to B = 1024 the partial last blocks of the snapshots take their
+// checked path in the same launch (as in the plain form); at B = 2048 that
+// path would add spills to every block, so they go to encode_batch_tails.
+template <int ITEMS>
+constexpr bool kDirectTails = ITEMS <= 16;
+
 template <int ITEMS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ITEMS == 16 ? 3 : 2))) void encode_batch_direct(
     const EncodeArgs* __restrict__ jobs, const BatchLaunch* __restrict__ L) {
     constexpr uint32_t B = 64 * ITEMS;
+    constexpr int EARLY = ITEMS == 16 ? 0 : 3;
     __shared__ EncodeSmem<ITEMS> sm;
     const uint32_t g = blockIdx.x;
-    if (g >= L->total_full) return;
-    const uint32_t* prefix = L->full_prefix;
+    if (g >= (kDirectTails<ITEMS> ? L->total_blocks : L->total_full)) return;
+    const uint32_t* prefix = kDirectTails<ITEMS> ? L->block_prefix : L->full_prefix;
     const uint32_t j = find_job(prefix, L->njobs, g);
-    encode_block<ITEMS, true, false, ITEMS == 16 ? 0 : 3>(jobs[j], g - prefix[j], B, sm.buf);
+    const EncodeArgs& a = jobs[j];
+    const uint32_t b = g - prefix[j];
+    if constexpr (kDirectTails<ITEMS>) {
+        const uint64_t left = a.n - (uint64_t)b * B;
+        if (left < B) {
+            encode_block<ITEMS, false, false, EARLY>(a, b, (uint32_t)left, sm.buf);
+            return;
+        }
+    }
+    encode_block<ITEMS, true, false, EARLY>(a, b, B, sm.buf);
 }
 
 // The partial last block of each snapshot that has one.
@@ -1147,9 +1162,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ITEMS == 16 
 template <int ITEMS>
 void launch_encode_batch_items(const EncodeArgs* jobs, const BatchLaunch* L, const BatchShape& S,
                                hipStream_t s) {
-    if (S.grid) hipLaunchKernelGGL(encode_batch<ITEMS>, dim3(S.grid), dim3(64), 0, s, jobs, L);
-    else hipLaunchKernelGGL(encode_batch_direct<ITEMS>, dim3(S.direct_grid), dim3(64), 0, s, jobs, L);
-    hipLaunchKernelGGL(encode_batch_tails<ITEMS>, dim3(S.tail_grid), dim3(64), 0, s, jobs, L);
+    if (S.grid) {
+        hipLaunchKernelGGL(encode_batch<ITEMS>, dim3(S.grid), dim3(64), 0, s, jobs, L);
+        hipLaunchKernelGGL(encode_batch_tails<ITEMS>, dim3(S.tail_grid), dim3(64), 0, s, jobs, L);
+    } else {
+        hipLaunchKernelGGL(encode_batch_direct<ITEMS>, dim3(S.direct_grid), dim3(64), 0, s, jobs, L);
+        if (!kDirectTails<ITEMS>)
+            hipLaunchKernelGGL(encode_batch_tails<ITEMS>, dim3(S.tail_grid), dim3(64), 0, s, jobs, L);
+    }
 }
 
 }  // namespace

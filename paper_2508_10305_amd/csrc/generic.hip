@@ -471,14 +471,26 @@ template <uint32_t CB>
 __global__ __launch_bounds__(256) void gen_encode_deferred_batch(const EncodeArgs* __restrict__ jobs,
                                                                  const BatchLaunch* __restrict__ L) {
     __shared__ __align__(16) GenEncodeSmem<CB> sm;
+    __shared__ uint32_t counts[kT];
     const uint32_t njobs = L->njobs;
-    for (uint32_t j = 0; j < njobs; j++) {
-        const EncodeArgs& a = jobs[j];
-        const uint32_t count = *a.defer_count;
-        for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
-            gen_encode_block<CB>(a, a.defer[k], sm);
-            __syncthreads();
+    for (uint32_t j0 = 0; j0 < njobs; j0 += kT) {
+        // the deferred counts of kT jobs at once, one job per thread: when
+        // nothing is deferred (the common case) the walk costs one memory
+        // round trip per kT jobs instead of one per job
+        const uint32_t jt = j0 + threadIdx.x;
+        const uint32_t c = jt < njobs ? *jobs[jt].defer_count : 0u;
+        counts[threadIdx.x] = c;
+        if (!__syncthreads_or(c != 0u)) continue;
+        const uint32_t jn = njobs - j0 < kT ? njobs - j0 : kT;
+        for (uint32_t i = 0; i < jn; i++) {
+            const uint32_t count = counts[i];
+            const EncodeArgs& a = jobs[j0 + i];
+            for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
+                gen_encode_block<CB>(a, a.defer[k], sm);
+                __syncthreads();
+            }
         }
+        __syncthreads();  // counts[] is read before the next group replaces it
     }
 }
 

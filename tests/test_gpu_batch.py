@@ -271,7 +271,7 @@ def test_batch_reports_corrupt_stream(gpz):
     b.close()
 
 
-@pytest.mark.parametrize("B", [256, 2048])
+@pytest.mark.parametrize("B", [256, 512, 2048])
 @pytest.mark.parametrize("grid", [300, 0])
 def test_batch_other_block_sizes(gpz, orc, B, grid):
     """Batched streams and decoded fields equal the oracle's at other block
