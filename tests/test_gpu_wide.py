@@ -227,3 +227,32 @@ def test_batch_with_wide_jobs(gpz, orc):
         b.decompress()
         check_batch(b, outs, decs, ref, f"wide batch grid={grid}")
         b.close()
+
+
+def test_batch_wide_jobs_beyond_the_first_256(gpz, orc):
+    """300 jobs, wide ones among the first 256 and past them: the batched
+    walk over blocks left to the generic encoder reads the jobs' deferred
+    counts 256 at a time, and every group must be walked."""
+    from paper_2508_10305_amd import synth
+    from test_gpu_batch import build_batch, check_batch, oracle_results
+    rng = np.random.default_rng(7)
+    jobs = []
+    for j in range(300):
+        if j in (3, 255, 256, 290):
+            jobs.append((widegrid(2 * 1024 + 5 * j % 97, 3, seed=100 + j), 2.0 ** -12))
+        else:
+            n = int(rng.integers(100, 3000))
+            jobs.append((synth.clusters(n, seed=1000 + j), float(rng.choice([1e-3, 1e-4]))))
+    ref = oracle_results(orc, jobs)
+    wide = [j for j, r in enumerate(ref) if (r[0].view(np.uint32)[1] >> 17) & 1]
+    assert wide == [3, 255, 256, 290]
+    from paper_2508_10305_amd.batch import default_config
+    for grid in (97, 0):
+        cfg = default_config()
+        cfg.grid = grid
+        say(f"[case] batch of 300 with wide jobs grid={grid}")
+        b, fields, outs, decs, ebs = build_batch(gpz, jobs, cfg)
+        b.compress()
+        b.decompress()
+        check_batch(b, outs, decs, ref, f"300 jobs grid={grid}")
+        b.close()
