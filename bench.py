@@ -824,7 +824,7 @@ def bench_batched(args):
                for j in range(len(specs)))
     C = int(sizes.sum())
     rec = {
-        "metric": "batched compress+decompress GB/s (persistent fused kernels under a HIP graph)",
+        "metric": "batched compress+decompress GB/s (one launch per stage for all snapshots, replayed from a HIP graph)",
         "form": "batched",
         "value": round(2 * S / (ms_batch * 1e-3) / 1e9, 2),
         "unit": "GB/s",
