@@ -111,7 +111,8 @@ CompressWs layout(uint64_t n, uint32_t F, uint32_t B, uint32_t vw, char* base) {
     o = align256(o + nb * w.slot_words * 4ull);
     // look-back words, ticket, total, deferred-block count, wide flag and the
     // superblock sums are contiguous: one fill clears what either compaction
-    // needs zeroed
+    // needs zeroed (the three-step one starts it at the ticket, after the
+    // look-back words only the single pass uses)
     w.state = ws_at<uint64_t>(base, o);
     w.ticket = ws_at<uint32_t>(base, o + nb * 8);
     w.total = ws_at<uint64_t>(base, o + nb * 8 + 8);
