@@ -480,6 +480,7 @@ __global__ __launch_bounds__(256) void gen_encode_deferred_batch(const EncodeArg
         const uint32_t jt = j0 + threadIdx.x;
         const uint32_t c = jt < njobs ? *jobs[jt].defer_count : 0u;
         counts[threadIdx.x] = c;
+        __syncthreads();  // every count is in LDS before any thread reads them
         if (!__syncthreads_or(c != 0u)) continue;
         const uint32_t jn = njobs - j0 < kT ? njobs - j0 : kT;
         for (uint32_t i = 0; i < jn; i++) {
