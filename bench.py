@@ -427,6 +427,39 @@ def main():
                    if avg[k] and algo[k] else None}
                for k in avg}
 
+    # The same step captured once in a HIP graph and replayed: the plain
+    # calls' launches without the host between them (the async calls are
+    # capturable).  Reported beside the eager step, which stays the headline;
+    # every replay's stream and decoded fields must equal the eager ones.
+    ref_stream = stream.clone()
+    ref_outs = [o.clone() for o in outs]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+
+    def replay_matches():
+        torch.cuda.synchronize()
+        return (int(err.item()) == 0 and int(comp.nbytes_dev.item()) == C and
+                torch.equal(comp.out[:C], ref_stream) and
+                all(torch.equal(o, r) for o, r in zip(outs, ref_outs)))
+    graph.replay()
+    graph_same = replay_matches()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    g1.record()
+    torch.cuda.synchronize()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    graph_same = graph_same and replay_matches()
+    del graph, ref_outs
+
     # A/B: single-pass look-back compaction (encoder places its own record)
     # against the default three launches (encode, scan, copy); same stream
     p1 = gpz.params(F, single_pass=True)
@@ -562,6 +595,9 @@ def main():
         "raw_blocks": raw_blocks,
         "kernels": kernels,
         "compaction_ab": compaction_ab,
+        "graph_replayed_step": {"ms_per_step": round(graph_ms, 4),
+                                "GBps": round(2 * S / (graph_ms * 1e-3) / 1e9, 2),
+                                "streams_identical_to_eager": graph_same},
         "field_range_ms": round(range_ms, 3),
         "rel_eb_step_ms": round(rel_eb_step_ms, 4),
         **extra,
