@@ -112,6 +112,20 @@ def test_cosmology_md_lidar_scaled(gpz, orc, rel):
         check_case(gpz, orc, host, eb, label=f"{name} rel {rel}")
 
 
+@pytest.mark.parametrize("K", [3, 5])
+def test_local_storage_orders(gpz, orc, K):
+    """File-like storage orders (particles stored near their neighbours:
+    small blocks, narrow codes, short runs of segment IDs) against the
+    oracle, and a shuffled crystal as the opposite case (md's local order is
+    its lattice order)."""
+    from paper_2508_10305_amd import synth
+    sets = [(k, "local") for k in ("clusters", "cosmology", "lidar", "md")] + [("md", "shuffled")]
+    for kind, order in sets:
+        host = synth.make(kind, 300_000, seed=11, order=order)
+        eb = orc.rel_ebs(host, 1e-3)
+        check_case(gpz, orc, host, eb, K=K, label=f"{kind} {order} K={K}")
+
+
 def test_specials_and_outliers(gpz, orc):
     rng = np.random.default_rng(5)
     n = 7000
